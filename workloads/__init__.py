@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs for the match-count workloads.
+
+This module is the only code shared by the CPU oracle's tests and the GPU
+path.  It draws random numbers and lays them out; it holds none of the
+method's arithmetic (no counting, no hashing, no selection).
+
+Workloads (the paper's datasets are not available; these stand in for them):
+
+* ``tiny``        10,000 objects x 16 dims, values uniform in [0, 64); 100
+                  queries of one item per dim, [v-2, v+2] around a random
+                  object's value; k = 10.
+* ``relational``  1,000,000 x 32 dims, 256 buckets, per-dim finite Zipf(1.1)
+                  (P(b) proportional to (b+1)^-1.1, bucket 0 is the head);
+                  1,024 queries, one range item per dim centred on a random
+                  object's value with width uniform in {0..8}; k = 100.
+                  Stands in for the Adult relational table (Section 6.1.1).
+* ``ann``         1,000,000 float32 points in 128-d from a 64-component
+                  Gaussian mixture clipped at 0; 4,096 perturbed queries;
+                  237 E2LSH functions (w = 4.0) re-hashed into 8,192 buckets;
+                  k = 100.  Stands in for SIFT (Section 6.1.1).
+* ``uneven``      10,000,000 x 64 dims, 1,024 buckets, Zipf(1.1); 16,384
+                  queries with 4..512 items each; k = 100.
+
+Every generator takes explicit sizes so that tests can draw scaled-down
+instances with the same structure.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+BASE_SEED = 1603083900
+CONFIG_IDS = {"tiny": 1, "relational": 2, "ann": 3, "uneven": 4, "serving": 5}
+
+
+def rng_streams(config_id: int, salt: int = 0):
+    """Independent child generators (objects, queries, lsh) for one workload."""
+    ss = np.random.SeedSequence(BASE_SEED + config_id + salt)
+    return [np.random.default_rng(s) for s in ss.spawn(3)]
+
+
+# ----------------------------------------------------------------------------
+# value distributions
+# ----------------------------------------------------------------------------
+
+def zipf_cdf(V: int, a: float = 1.1) -> np.ndarray:
+    """CDF of the finite Zipf law P(b) ~ (b+1)^-a on b in [0, V)."""
+    w = np.arange(1, V + 1, dtype=np.float64) ** (-a)
+    c = np.cumsum(w)
+    return c / c[-1]
+
+
+def objects_uniform(rng, n: int, d: int, V: int) -> np.ndarray:
+    return rng.integers(0, V, size=(n, d), dtype=np.uint32)
+
+
+def objects_zipf(rng, n: int, d: int, V: int, a: float = 1.1,
+                 chunk_rows: int = 1 << 20) -> np.ndarray:
+    """Independent per-dim finite Zipf values, drawn by inverse CDF."""
+    cdf = zipf_cdf(V, a)
+    out = np.empty((n, d), dtype=np.uint32)
+    for r0 in range(0, n, chunk_rows):
+        r1 = min(n, r0 + chunk_rows)
+        u = rng.random((r1 - r0, d))
+        idx = np.searchsorted(cdf, u, side="right")
+        np.minimum(idx, V - 1, out=idx)
+        out[r0:r1] = idx.astype(np.uint32)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# query layouts: CSR of items, each item = (dim, lo, hi) inclusive
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Queries:
+    q_offsets: np.ndarray  # uint64 [nq+1]
+    items: np.ndarray      # uint32 [n_items, 3] (dim, lo, hi)
+
+    @property
+    def n_queries(self) -> int:
+        return len(self.q_offsets) - 1
+
+    def items_of(self, q: int) -> np.ndarray:
+        return self.items[self.q_offsets[q]:self.q_offsets[q + 1]]
+
+    def max_items(self) -> int:
+        if self.n_queries == 0:
+            return 0
+        return int(np.max(np.diff(self.q_offsets.astype(np.int64))))
+
+    def subset(self, qs) -> "Queries":
+        qs = list(qs)
+        lens = [int(self.q_offsets[q + 1] - self.q_offsets[q]) for q in qs]
+        off = np.zeros(len(qs) + 1, dtype=np.uint64)
+        off[1:] = np.cumsum(lens, dtype=np.uint64)
+        if qs:
+            items = np.concatenate([self.items_of(q) for q in qs]).astype(np.uint32)
+        else:
+            items = np.zeros((0, 3), dtype=np.uint32)
+        return Queries(off, items.reshape(-1, 3))
+
+
+def queries_halfwidth(rng, values: np.ndarray, V: int, nq: int, half: int) -> Queries:
+    """One item per dim: [v-half, v+half] clipped, v = a random object's value."""
+    n, d = values.shape
+    objs = rng.integers(0, n, size=nq)
+    c = values[objs].astype(np.int64)                       # [nq, d]
+    lo = np.clip(c - half, 0, V - 1)
+    hi = np.clip(c + half, 0, V - 1)
+    dims = np.broadcast_to(np.arange(d, dtype=np.int64), (nq, d))
+    items = np.stack([dims, lo, hi], axis=-1).reshape(-1, 3).astype(np.uint32)
+    off = (np.arange(nq + 1, dtype=np.uint64) * np.uint64(d))
+    return Queries(off, items)
+
+
+def queries_random_width(rng, values: np.ndarray, V: int, nq: int, wmax: int = 8) -> Queries:
+    """One item per dim centred on one random object's value per query.
+
+    Width w ~ U{0..wmax} per item; lo = c - floor(w/2), hi = lo + w, clipped.
+    """
+    n, d = values.shape
+    objs = rng.integers(0, n, size=nq)
+    c = values[objs].astype(np.int64)
+    w = rng.integers(0, wmax + 1, size=(nq, d))
+    lo = c - w // 2
+    hi = lo + w
+    lo = np.clip(lo, 0, V - 1)
+    hi = np.clip(hi, 0, V - 1)
+    dims = np.broadcast_to(np.arange(d, dtype=np.int64), (nq, d))
+    items = np.stack([dims, lo, hi], axis=-1).reshape(-1, 3).astype(np.uint32)
+    off = (np.arange(nq + 1, dtype=np.uint64) * np.uint64(d))
+    return Queries(off, items)
+
+
+def queries_uneven(rng, values: np.ndarray, V: int, nq: int, smin: int = 4,
+                   smax: int = 512, wmax: int = 8) -> Queries:
+    """s ~ U{smin..smax} items per query; item j is on dim j mod d, centred on
+    an independently drawn random object's value, width as above."""
+    n, d = values.shape
+    s = rng.integers(smin, smax + 1, size=nq)
+    off = np.zeros(nq + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(s, dtype=np.uint64)
+    total = int(off[-1])
+    j = np.arange(total, dtype=np.int64) - np.repeat(off[:-1].astype(np.int64), s)
+    dims = j % d
+    objs = rng.integers(0, n, size=total)
+    c = values[objs, dims].astype(np.int64)
+    w = rng.integers(0, wmax + 1, size=total)
+    lo = np.clip(c - w // 2, 0, V - 1)
+    hi = np.clip(c - w // 2 + w, 0, V - 1)
+    items = np.stack([dims, lo, hi], axis=-1).astype(np.uint32)
+    return Queries(off, items)
+
+
+def queries_exact(sig: np.ndarray) -> Queries:
+    """Item i = (i, sig[i], sig[i]) for every hash function i of each query."""
+    nq, m = sig.shape
+    dims = np.broadcast_to(np.arange(m, dtype=np.uint32), (nq, m))
+    items = np.stack([dims, sig, sig], axis=-1).reshape(-1, 3).astype(np.uint32)
+    off = np.arange(nq + 1, dtype=np.uint64) * np.uint64(m)
+    return Queries(off, items)
+
+
+# ----------------------------------------------------------------------------
+# relational-style workloads
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Relational:
+    name: str
+    values: np.ndarray     # uint32 [n, d], each < V
+    V: int
+    queries: Queries
+    k: int
+
+    @property
+    def n(self) -> int:
+        return self.values.shape[0]
+
+    @property
+    def d(self) -> int:
+        return self.values.shape[1]
+
+
+def tiny(n: int = 10_000, d: int = 16, V: int = 64, nq: int = 100, k: int = 10,
+         half: int = 2, salt: int = 0) -> Relational:
+    ro, rq, _ = rng_streams(CONFIG_IDS["tiny"], salt)
+    values = objects_uniform(ro, n, d, V)
+    return Relational("tiny", values, V, queries_halfwidth(rq, values, V, nq, half), k)
+
+
+def relational(n: int = 1_000_000, d: int = 32, V: int = 256, nq: int = 1024,
+               k: int = 100, wmax: int = 8, a: float = 1.1, salt: int = 0) -> Relational:
+    ro, rq, _ = rng_streams(CONFIG_IDS["relational"], salt)
+    values = objects_zipf(ro, n, d, V, a)
+    return Relational("relational", values, V, queries_random_width(rq, values, V, nq, wmax), k)
+
+
+def uneven(n: int = 10_000_000, d: int = 64, V: int = 1024, nq: int = 16_384,
+           k: int = 100, smin: int = 4, smax: int = 512, wmax: int = 8,
+           a: float = 1.1, salt: int = 0) -> Relational:
+    ro, rq, _ = rng_streams(CONFIG_IDS["uneven"], salt)
+    values = objects_zipf(ro, n, d, V, a)
+    return Relational("uneven", values, V,
+                      queries_uneven(rq, values, V, nq, smin, smax, wmax), k)
+
+
+# ----------------------------------------------------------------------------
+# tau-ANN workload: raw points and LSH parameters (hashing is done elsewhere)
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class AnnInputs:
+    points: np.ndarray     # float32 [n, dim]
+    queries: np.ndarray    # float32 [nq, dim]
+    a: np.ndarray          # float32 [m, dim]   projection vectors, N(0, 1)
+    b: np.ndarray          # float32 [m]        offsets, U[0, w)
+    w: float
+    rehash: np.ndarray     # uint64 [2m]        (A_i odd, B_i) interleaved
+    log2_buckets: int
+    k: int
+
+
+def ann(n: int = 1_000_000, dim: int = 128, nq: int = 4096, m: int = 237,
+        w: float = 4.0, log2_buckets: int = 13, components: int = 64,
+        sigma: float = 0.5, qsigma: float = 0.1, k: int = 100,
+        salt: int = 0, chunk_rows: int = 1 << 18) -> AnnInputs:
+    ro, rq, rl = rng_streams(CONFIG_IDS["ann"], salt)
+    means = ro.uniform(0.0, 8.0, size=(components, dim)).astype(np.float32)
+    points = np.empty((n, dim), dtype=np.float32)
+    for r0 in range(0, n, chunk_rows):
+        r1 = min(n, r0 + chunk_rows)
+        comp = ro.integers(0, components, size=r1 - r0)
+        x = means[comp] + np.float32(sigma) * ro.standard_normal((r1 - r0, dim), dtype=np.float32)
+        np.maximum(x, 0.0, out=x)
+        points[r0:r1] = x
+    src = rq.integers(0, n, size=nq)
+    queries = points[src] + np.float32(qsigma) * rq.standard_normal((nq, dim), dtype=np.float32)
+    np.maximum(queries, 0.0, out=queries)
+    a = rl.standard_normal((m, dim), dtype=np.float32)
+    b = rl.uniform(0.0, w, size=m).astype(np.float32)
+    b = np.minimum(b, np.nextafter(np.float32(w), np.float32(0)))
+    A = rl.integers(0, 2**63, size=m, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    B = rl.integers(0, 2**63, size=m, dtype=np.uint64) * np.uint64(2) + \
+        rl.integers(0, 2, size=m, dtype=np.uint64)
+    rehash = np.empty(2 * m, dtype=np.uint64)
+    rehash[0::2] = A
+    rehash[1::2] = B
+    return AnnInputs(points, queries.astype(np.float32), a, b, float(w), rehash,
+                     int(log2_buckets), k)
+
+
+def random_small(rng, n: int, d: int, V: int, nq: int, max_items: int,
+                 allow_empty: bool = True) -> Relational:
+    """Tiny adversarial instances: random items on random dims (dims may
+    repeat, ranges may overlap, be empty after clipping or exceed [0, V))."""
+    values = rng.integers(0, V, size=(n, d), dtype=np.uint32)
+    lens = rng.integers(0 if allow_empty else 1, max_items + 1, size=nq)
+    off = np.zeros(nq + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lens, dtype=np.uint64)
+    total = int(off[-1])
+    dims = rng.integers(0, d, size=total)
+    lo = rng.integers(0, V + 2, size=total)
+    hi = rng.integers(0, V + 2, size=total)
+    # hi may be below lo (empty item) and either bound may lie past V-1
+    items = np.stack([dims, lo, hi], axis=-1).astype(np.uint32).reshape(-1, 3)
+    return Relational("random_small", values, V, Queries(off, items), 1)
