@@ -1,0 +1,197 @@
+/*
+ * libgenie -- match-count search with a count priority queue on MI355X (gfx950).
+ *
+ * The method (GENIE, "A Generic Inverted Index Framework for Similarity
+ * Search on the GPU"):
+ *   - Section 2.1, Definition 2.1: an object is one value per dimension; a
+ *     query is a list of items (dim, lo, hi); MC(Q, O) counts the items that
+ *     contain O's value on the item's dimension (ranges inclusive, Example
+ *     2.1).  The answer is the k objects of largest MC.
+ *   - Section 3.2: an inverted index on the GPU, keyword = (dim, value),
+ *     postings = ids of the objects holding that keyword.
+ *   - Section 3.3: the count priority queue (c-PQ): Bitmap Counter, Gate
+ *     (ZipperArray + AuditThreshold, Algorithm 1), Hash Table with a modified
+ *     Robin Hood scheme; Theorem 3.1 gives MC_k = AT - 1.
+ *   - Section 4.1.2 / 4.2.3: LSH signatures (E2LSH, then a re-hash into D
+ *     buckets) turn points into match-count objects for tau-ANN search.
+ *
+ * Answer order: count descending, then id ascending (the paper breaks ties
+ * at the k-th count randomly; a fixed order makes every answer unique and
+ * checkable bit for bit).  Row q lists min(k, n) objects over ALL n objects
+ * (objects with count 0 included, smallest ids first); slots past n hold
+ * (id = UINT32_MAX, count = 0).
+ *
+ * Conventions for every call:
+ *   - Return value: GENIE_OK (0) or a negative GENIE_E* code.  No exception
+ *     or abort crosses this interface.  On error, output contents are
+ *     unspecified and genie_last_error() describes the failure.
+ *   - The caller owns every buffer it passes and keeps it alive for the
+ *     call (for *_async calls: until the stream has passed the call).  The
+ *     library owns an index from genie_build_index until genie_free_index.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the current device (for example a torch tensor's
+ *     data_ptr()).  Streams are hipStream_t passed as void*; NULL means the
+ *     default (null) stream.
+ *   - A const genie_index* may be searched concurrently from several host
+ *     threads and streams, each with its own workspace.
+ */
+#ifndef GENIE_H
+#define GENIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GENIE_OK 0
+#define GENIE_EINVAL (-22)   /* bad pointer, size, dimension, k, ... */
+#define GENIE_ENOMEM (-12)   /* host or device allocation failed */
+#define GENIE_EDEVICE (-5)   /* a HIP call failed */
+#define GENIE_ERANGE (-34)   /* a query exceeds the limits below */
+
+/* Limits of one search call. */
+#define GENIE_MAX_K 1024          /* results per query */
+#define GENIE_MAX_ITEMS 1024      /* items per query (bounds the count) */
+#define GENIE_TILE_OBJECTS 65536  /* objects per index tile (16-bit local ids) */
+
+/* Device status flags, OR-ed into the first word of a search workspace. */
+#define GENIE_STATUS_BAD_DIM 1u       /* an item named dim >= n_dims (treated as empty) */
+#define GENIE_STATUS_TOO_MANY_ITEMS 2u /* a query had more items than max_items (row padded) */
+#define GENIE_STATUS_BAD_OFFSETS 4u    /* a query's offsets were invalid (row padded) */
+
+typedef struct genie_index genie_index; /* opaque, owned by the library */
+
+/* One query item: the keywords (dim, v) with lo <= v <= hi (Example 2.1).
+ * hi is capped at n_buckets-1; lo > hi (after the cap) is an empty item.
+ * Several items may name the same dim; each contributes on its own
+ * (MC sums over items, Definition 2.1). */
+typedef struct {
+    uint32_t dim, lo, hi;
+} genie_item;
+
+typedef struct {
+    uint64_t n_objects;
+    uint32_t n_dims;
+    uint32_t n_buckets;
+    uint32_t n_tiles;          /* ceil(n_objects / GENIE_TILE_OBJECTS) */
+    uint32_t tile_objects;     /* GENIE_TILE_OBJECTS */
+    uint64_t n_postings;       /* n_objects * n_dims */
+    uint64_t device_bytes;     /* device memory held by the index */
+} genie_index_info;
+
+/*
+ * Build the inverted index of Section 3.2 (List Array + Position Map) and
+ * upload it to the current device.
+ *   values:    host, n_objects * n_dims uint32, row-major (object-major);
+ *              values[o*n_dims + j] is object o's value on dim j, which must
+ *              be < n_buckets (keyword = (j, value), Section 2.1).
+ *   n_objects: 1 .. 2^32 - 1; n_dims >= 1; n_buckets >= 1;
+ *              n_dims * n_buckets < 2^32.
+ *   out:       receives the new index.
+ * Layout on the device: objects are cut into tiles of GENIE_TILE_OBJECTS;
+ * postings are stored tile-major, then keyword-major, as 16-bit ids local to
+ * the tile in ascending order, so that every keyword list restricted to a
+ * tile is one contiguous run and the runs of one dimension are adjacent.
+ * Errors: GENIE_EINVAL (null pointer, size, value >= n_buckets),
+ * GENIE_ENOMEM, GENIE_EDEVICE.
+ */
+int genie_build_index(const uint32_t *values, uint64_t n_objects, uint32_t n_dims,
+                      uint32_t n_buckets, genie_index **out);
+
+/* Free an index and its device memory.  NULL is ignored. */
+void genie_free_index(genie_index *ix);
+
+/* Describe an index.  Errors: GENIE_EINVAL. */
+int genie_index_info_get(const genie_index *ix, genie_index_info *out);
+
+/*
+ * Top-k match-count search (Definition 2.1 scored, c-PQ of Section 3.3
+ * selecting), synchronous, host buffers.
+ *   q_offsets: host, n_queries+1 uint64; query q owns
+ *              items[q_offsets[q] .. q_offsets[q+1]-1]; q_offsets[0] = 0,
+ *              non-decreasing.
+ *   items:     host, q_offsets[n_queries] items.
+ *   k:         1 .. GENIE_MAX_K.  Each query has at most GENIE_MAX_ITEMS items.
+ *   out_ids, out_counts: host, n_queries * k uint32 each, row q at q*k.
+ * Errors: GENIE_EINVAL (dim >= n_dims, k out of range, bad offsets, null
+ * pointer with n_queries > 0), GENIE_ERANGE (too many items), GENIE_ENOMEM,
+ * GENIE_EDEVICE.  n_queries = 0 is a no-op.
+ */
+int genie_search(const genie_index *ix, const uint64_t *q_offsets, const genie_item *items,
+                 uint32_t n_queries, uint32_t k, uint32_t *out_ids, uint32_t *out_counts);
+
+/*
+ * Bytes of device workspace that genie_search_async needs for n_queries
+ * queries at this k (0 on bad arguments).
+ */
+size_t genie_search_workspace_size(const genie_index *ix, uint32_t n_queries, uint32_t k);
+
+/*
+ * Same search, enqueued on a stream, all buffers on the device.
+ *   d_q_offsets, d_items, d_out_ids, d_out_counts: as in genie_search, device.
+ *   n_items:     number of items in d_items.  A query whose offsets are
+ *                decreasing or reach past n_items is answered with padding
+ *                and flags GENIE_STATUS_BAD_OFFSETS; no item outside
+ *                d_items is read.
+ *   max_items:   an upper bound on the items of every query in this call
+ *                (1 .. GENIE_MAX_ITEMS; it fixes the counter width).  A query
+ *                with more items is answered with padding and flags
+ *                GENIE_STATUS_TOO_MANY_ITEMS.
+ *   d_workspace: device, >= genie_search_workspace_size(ix, n_queries, k)
+ *                bytes, 256-byte aligned.  After the stream passes the call,
+ *                its first uint32 holds the OR of GENIE_STATUS_* flags, and
+ *                the following uint64 words hold: postings scanned, tiles whose
+ *                hash table overflowed (answered exactly from the counters),
+ *                hash-table insertions.  Calls that share a workspace must be
+ *                ordered on one stream.
+ *   stream:      hipStream_t or NULL.
+ * Host-side checks only (k, max_items, pointers); item contents are checked
+ * on the device (bad dims flag GENIE_STATUS_BAD_DIM and act as empty items).
+ */
+int genie_search_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                       const genie_item *d_items, uint64_t n_items, uint32_t n_queries,
+                       uint32_t max_items,
+                       uint32_t k, uint32_t *d_out_ids, uint32_t *d_out_counts,
+                       void *d_workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Full match-count vectors (the scan-and-count step of Section 3.2 with the
+ * Bitmap Counter of Section 3.3.1), for checking and analysis.
+ *   d_out_counts: device, n_queries * n_objects uint32; row q at q*n_objects.
+ * Other arguments as genie_search_async (workspace from
+ * genie_search_workspace_size(ix, n_queries, 1)).
+ */
+int genie_match_count_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                            const genie_item *d_items, uint64_t n_items, uint32_t n_queries,
+                            uint32_t max_items, uint32_t *d_out_counts,
+                            void *d_workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * LSH signatures (Section 4.1.2 object transform with the E2LSH family of
+ * Section 4.2.3):  h_i(p) = floor((a_i . p + b_i) / w), computed in float32
+ * (products and a sum in a fixed order), then re-hashed into
+ * [0, 2^log2_buckets):  u = the 32-bit two's complement pattern of h_i
+ * zero-extended to 64 bits,  r_i = ((A_i * u + B_i) mod 2^64) >> (64 - log2_buckets).
+ *   d_points: device, n * dim float32, row-major.
+ *   d_a:      device, m * dim float32 (row i = a_i).
+ *   d_b:      device, m float32.
+ *   w:        bucket width > 0.
+ *   d_rehash: device, 2*m uint64, (A_0, B_0, A_1, B_1, ...).
+ *   log2_buckets: 1 .. 32.
+ *   d_out_sig: device, n * m uint32, row-major (object = [r_1(h_1(p)), ...]).
+ * Errors: GENIE_EINVAL, GENIE_EDEVICE.
+ */
+int genie_lsh_signatures(const float *d_points, uint64_t n, uint32_t dim, const float *d_a,
+                         const float *d_b, float w, uint32_t m, const uint64_t *d_rehash,
+                         uint32_t log2_buckets, uint32_t *d_out_sig, void *stream);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *genie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENIE_H */

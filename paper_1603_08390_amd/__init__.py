@@ -1,0 +1,274 @@
+"""Python binding of libgenie (match-count search with c-PQ on MI355X).
+
+Argument marshalling only: every step of the search runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.  The functions
+carry the names of the C-ABI calls in ``include/genie.h``.
+
+The library must be built (``python -m paper_1603_08390_amd.build`` or
+``__graft_entry__.build()``); importing works without it, but every call
+raises ``GenieError`` when ``libgenie.so`` is missing -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgenie.so")
+
+GENIE_OK = 0
+GENIE_EINVAL = -22
+GENIE_ENOMEM = -12
+GENIE_EDEVICE = -5
+GENIE_ERANGE = -34
+GENIE_MAX_K = 1024
+GENIE_MAX_ITEMS = 1024
+GENIE_TILE_OBJECTS = 65536
+STATUS_BAD_DIM = 1
+STATUS_TOO_MANY_ITEMS = 2
+STATUS_BAD_OFFSETS = 4
+
+EXPORTED = (
+    "genie_build_index", "genie_free_index", "genie_index_info_get", "genie_search",
+    "genie_search_workspace_size", "genie_search_async", "genie_match_count_async",
+    "genie_lsh_signatures", "genie_last_error",
+)
+
+
+class GenieError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libgenie error {code}: {msg}")
+        self.code = code
+
+
+class _IndexInfo(ctypes.Structure):
+    _fields_ = [("n_objects", ctypes.c_uint64), ("n_dims", ctypes.c_uint32),
+                ("n_buckets", ctypes.c_uint32), ("n_tiles", ctypes.c_uint32),
+                ("tile_objects", ctypes.c_uint32), ("n_postings", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libgenie.so; raises GenieError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GenieError(GENIE_EDEVICE, f"{LIB_PATH} is not built; run "
+                         "python -m paper_1603_08390_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    lib.genie_build_index.argtypes = [vp, u64, u32, u32, ctypes.POINTER(vp)]
+    lib.genie_build_index.restype = ctypes.c_int
+    lib.genie_free_index.argtypes = [vp]
+    lib.genie_free_index.restype = None
+    lib.genie_index_info_get.argtypes = [vp, ctypes.POINTER(_IndexInfo)]
+    lib.genie_index_info_get.restype = ctypes.c_int
+    lib.genie_search.argtypes = [vp, vp, vp, u32, u32, vp, vp]
+    lib.genie_search.restype = ctypes.c_int
+    lib.genie_search_workspace_size.argtypes = [vp, u32, u32]
+    lib.genie_search_workspace_size.restype = sz
+    lib.genie_search_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, vp, vp, sz, vp]
+    lib.genie_search_async.restype = ctypes.c_int
+    lib.genie_match_count_async.argtypes = [vp, vp, vp, u64, u32, u32, vp, vp, sz, vp]
+    lib.genie_match_count_async.restype = ctypes.c_int
+    lib.genie_lsh_signatures.argtypes = [vp, u64, u32, vp, vp, ctypes.c_float, u32, vp, u32,
+                                         vp, vp]
+    lib.genie_lsh_signatures.restype = ctypes.c_int
+    lib.genie_last_error.argtypes = []
+    lib.genie_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != GENIE_OK:
+        raise GenieError(rc, load().genie_last_error().decode(errors="replace"))
+
+
+def _np_ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _dev_ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+@dataclass
+class IndexInfo:
+    n_objects: int
+    n_dims: int
+    n_buckets: int
+    n_tiles: int
+    tile_objects: int
+    n_postings: int
+    device_bytes: int
+
+
+class Index:
+    """genie_build_index: the inverted index of Section 3.2 on the device."""
+
+    def __init__(self, values: np.ndarray, n_buckets: int):
+        values = np.ascontiguousarray(values, dtype=np.uint32)
+        if values.ndim != 2:
+            raise ValueError("values must be [n_objects, n_dims]")
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.genie_build_index(_np_ptr(values), values.shape[0], values.shape[1],
+                                     int(n_buckets), ctypes.byref(h)))
+        self._h = h
+        info = _IndexInfo()
+        _check(lib.genie_index_info_get(self._h, ctypes.byref(info)))
+        self.info = IndexInfo(info.n_objects, info.n_dims, info.n_buckets, info.n_tiles,
+                              info.tile_objects, info.n_postings, info.device_bytes)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise GenieError(GENIE_EINVAL, "index is freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            load().genie_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def genie_build_index(values: np.ndarray, n_buckets: int) -> Index:
+    return Index(values, n_buckets)
+
+
+def genie_search(index: Index, q_offsets: np.ndarray, items: np.ndarray, k: int
+                 ) -> Tuple[np.ndarray, np.ndarray]:
+    """Synchronous search with host arrays; returns (ids, counts) [nq, k] uint32."""
+    q_offsets = np.ascontiguousarray(q_offsets, dtype=np.uint64)
+    items = np.ascontiguousarray(items, dtype=np.uint32).reshape(-1, 3)
+    nq = len(q_offsets) - 1
+    ids = np.zeros((max(nq, 0), k), dtype=np.uint32)
+    cts = np.zeros((max(nq, 0), k), dtype=np.uint32)
+    if nq <= 0:
+        return ids, cts
+    items_p = _np_ptr(items) if items.size else None
+    _check(load().genie_search(index.handle, _np_ptr(q_offsets), items_p, nq, int(k),
+                               _np_ptr(ids), _np_ptr(cts)))
+    return ids, cts
+
+
+def genie_search_workspace_size(index: Index, n_queries: int, k: int) -> int:
+    return int(load().genie_search_workspace_size(index.handle, int(n_queries), int(k)))
+
+
+def alloc_workspace(index: Index, n_queries: int, k: int, device="cuda"):
+    import torch
+    nbytes = genie_search_workspace_size(index, n_queries, k)
+    if nbytes == 0:
+        raise GenieError(GENIE_EINVAL, "bad workspace request")
+    # torch's caching allocator returns 256-byte aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def genie_search_async(index: Index, d_q_offsets, d_items, k: int, max_items: int,
+                       out_ids=None, out_counts=None, workspace=None, stream=None):
+    """Enqueue a search on a stream (device tensors); returns (ids, counts, workspace)."""
+    import torch
+    nq = d_q_offsets.numel() - 1
+    dev = d_q_offsets.device
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if out_counts is None:
+        out_counts = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = alloc_workspace(index, nq, k, dev)
+    if nq <= 0:
+        return out_ids, out_counts, workspace
+    _check(load().genie_search_async(index.handle, _dev_ptr(d_q_offsets), _dev_ptr(d_items),
+                                     d_items.numel() // 3, nq, int(max_items), int(k), _dev_ptr(out_ids),
+                                     _dev_ptr(out_counts), _dev_ptr(workspace),
+                                     workspace.numel(), _stream_handle(stream)))
+    return out_ids, out_counts, workspace
+
+
+def genie_match_count_async(index: Index, d_q_offsets, d_items, max_items: int,
+                            out=None, workspace=None, stream=None):
+    """Full match-count vectors [nq, n] (uint32 stored in int32 tensors)."""
+    import torch
+    nq = d_q_offsets.numel() - 1
+    dev = d_q_offsets.device
+    if out is None:
+        out = torch.empty((nq, index.info.n_objects), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = alloc_workspace(index, nq, 1, dev)
+    if nq <= 0:
+        return out, workspace
+    _check(load().genie_match_count_async(index.handle, _dev_ptr(d_q_offsets),
+                                          _dev_ptr(d_items), d_items.numel() // 3, nq, int(max_items), _dev_ptr(out),
+                                          _dev_ptr(workspace), workspace.numel(),
+                                          _stream_handle(stream)))
+    return out, workspace
+
+
+def genie_lsh_signatures(d_points, d_a, d_b, w: float, d_rehash, log2_buckets: int,
+                         out=None, stream=None):
+    """Signatures [n, m] (uint32 stored in int32) for float32 points on the device."""
+    import torch
+    n, dim = d_points.shape
+    m = d_a.shape[0]
+    if d_a.shape[1] != dim or d_b.numel() != m or d_rehash.numel() != 2 * m:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.int32, device=d_points.device)
+    _check(load().genie_lsh_signatures(_dev_ptr(d_points), n, dim, _dev_ptr(d_a), _dev_ptr(d_b),
+                                       float(w), m, _dev_ptr(d_rehash), int(log2_buckets),
+                                       _dev_ptr(out), _stream_handle(stream)))
+    return out
+
+
+def workspace_stats(workspace) -> dict:
+    """Status flags and counters left in a workspace by the last search."""
+    head = workspace[:32].cpu().numpy()
+    status = int(head[:4].view(np.uint32)[0])
+    stats = head[8:32].view(np.uint64)
+    return {"status": status, "postings_scanned": int(stats[0]),
+            "ht_overflow_tiles": int(stats[1]), "ht_inserts": int(stats[2])}
+
+
+def queries_to_device(q_offsets: np.ndarray, items: np.ndarray, device="cuda"):
+    """Copy a host query CSR to device tensors (uint64 offsets as int64)."""
+    import torch
+    off = torch.from_numpy(np.ascontiguousarray(q_offsets, dtype=np.uint64).view(np.int64))
+    items = np.ascontiguousarray(items, dtype=np.uint32).reshape(-1, 3)
+    if items.shape[0] == 0:
+        items = np.zeros((1, 3), dtype=np.uint32)   # never read; keeps the pointer valid
+    it = torch.from_numpy(items.view(np.int32))
+    return off.to(device), it.to(device)
+
+
+def as_uint32(t) -> np.ndarray:
+    """A device int32 tensor holding uint32 values, as a host uint32 array."""
+    return t.cpu().numpy().view(np.uint32)

@@ -1,0 +1,404 @@
+// Host side of libgenie: error reporting, index build (Section 3.2), the
+// synchronous search wrapper and argument checks of the C-ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace genie {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error("%s failed: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? GENIE_ENOMEM : GENIE_EDEVICE;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint32_t k) {
+    WorkspaceLayout L;
+    uint64_t pairs = (uint64_t)n_queries * ix->n_tiles;
+    L.status = 0;
+    L.tile_kth = 256;
+    L.cand = align256(L.tile_kth + pairs * sizeof(uint32_t));
+    L.total = align256(L.cand + pairs * (uint64_t)k * sizeof(uint64_t));
+    return L;
+}
+
+int search_shape(uint32_t max_items, uint32_t k, SearchShape *out) {
+    // Counter width b: counts reach at most max_items; one more code (all
+    // ones) marks an object already emitted during selection.
+    static const int widths[] = {4, 5, 6, 8, 10, 16};
+    int bits = 0;
+    for (int b : widths)
+        if ((uint64_t)max_items + 2 <= (1ull << b)) {
+            bits = b;
+            break;
+        }
+    if (!bits) {
+        set_error("max_items %u too large", max_items);
+        return GENIE_ERANGE;
+    }
+    // Hash table: live entries stay below about 2k (Theorem 3.1 with expiry
+    // of entries under AT-1); 4k slots keep probe sequences short.
+    uint32_t lg = 6;
+    while ((1u << lg) < 4u * k)
+        lg++;
+    uint32_t cpw = 32 / bits;
+    size_t words = 32 + (kTile + cpw - 1) / cpw + (1u << lg) + (max_items + 2) + 2ull * max_items;
+    out->bits = bits;
+    out->ht_log2 = lg;
+    out->lds_bytes = words * 4;
+    if (out->lds_bytes > kMaxLdsBytes) {
+        set_error("search needs %zu bytes of LDS (k=%u, max_items=%u); limit %zu",
+                  out->lds_bytes, k, max_items, kMaxLdsBytes);
+        return GENIE_ERANGE;
+    }
+    return GENIE_OK;
+}
+
+}  // namespace genie
+
+using namespace genie;
+
+extern "C" const char *genie_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// index build
+// ---------------------------------------------------------------------------
+
+extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
+                                 genie_index **out) {
+    clear_error();
+    if (!values || !out) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    *out = nullptr;
+    if (n == 0 || n >= 0xFFFFFFFFull || d == 0 || V == 0 || (uint64_t)d * V >= 0xFFFFFFFFull ||
+        (uint64_t)kTile * d >= 0xFFFFFFFFull) {
+        set_error("bad sizes n=%llu d=%u V=%u", (unsigned long long)n, d, V);
+        return GENIE_EINVAL;
+    }
+    const uint32_t T = (uint32_t)((n + kTile - 1) / kTile);
+    const uint64_t nkeys = (uint64_t)d * V;
+    const uint64_t npost = n * d;
+    const uint64_t pad = 64;  // aligned dword loads may touch one element past a run
+
+    std::vector<uint32_t> toff((uint64_t)T * (nkeys + 1));
+    std::vector<uint64_t> tile_base(T + 1);
+    std::vector<uint16_t> post(npost + pad, 0);
+    for (uint32_t t = 0; t <= T; t++)
+        tile_base[t] = std::min<uint64_t>((uint64_t)t * kTile, n) * d;
+
+    // Counting sort per tile, by keyword; objects visited in ascending id
+    // order so that every run is ascending.
+    std::atomic<int> bad{0};
+    std::atomic<uint32_t> next{0};
+    auto worker = [&]() {
+        std::vector<uint32_t> fill(nkeys);
+        for (;;) {
+            uint32_t t = next.fetch_add(1);
+            if (t >= T)
+                break;
+            uint64_t o0 = (uint64_t)t * kTile, o1 = std::min<uint64_t>(o0 + kTile, n);
+            uint32_t *row = &toff[(uint64_t)t * (nkeys + 1)];
+            for (uint64_t o = o0; o < o1; o++)
+                for (uint32_t j = 0; j < d; j++) {
+                    uint32_t v = values[o * d + j];
+                    if (v >= V) {
+                        bad.store(1);
+                        return;
+                    }
+                    row[(uint64_t)j * V + v + 1]++;
+                }
+            for (uint64_t key = 0; key < nkeys; key++)
+                row[key + 1] += row[key];
+            std::memcpy(fill.data(), row, nkeys * sizeof(uint32_t));
+            uint16_t *dst = &post[tile_base[t]];
+            for (uint64_t o = o0; o < o1; o++)
+                for (uint32_t j = 0; j < d; j++) {
+                    uint64_t key = (uint64_t)j * V + values[o * d + j];
+                    dst[fill[key]++] = (uint16_t)(o - o0);
+                }
+        }
+    };
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, T);
+    std::vector<std::thread> pool;
+    for (unsigned i = 0; i < nth; i++)
+        pool.emplace_back(worker);
+    for (auto &th : pool)
+        th.join();
+    if (bad.load()) {
+        set_error("a value is >= n_buckets (%u)", V);
+        return GENIE_EINVAL;
+    }
+
+    genie_index *ix = new (std::nothrow) genie_index;
+    if (!ix) {
+        set_error("host allocation failed");
+        return GENIE_ENOMEM;
+    }
+    ix->n = n;
+    ix->d = d;
+    ix->V = V;
+    ix->n_tiles = T;
+    ix->nkeys = nkeys;
+    ix->n_postings = npost;
+    hipError_t e = hipGetDevice(&ix->device);
+    size_t bp = post.size() * sizeof(uint16_t), bb = tile_base.size() * sizeof(uint64_t),
+           bt = toff.size() * sizeof(uint32_t);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->post, bp);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->tile_base, bb);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->toff, bt);
+    if (e == hipSuccess) e = hipMemcpy(ix->post, post.data(), bp, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ix->tile_base, tile_base.data(), bb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ix->toff, toff.data(), bt, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "index upload");
+        genie_free_index(ix);
+        return rc;
+    }
+    ix->device_bytes = bp + bb + bt;
+    *out = ix;
+    return GENIE_OK;
+}
+
+extern "C" void genie_free_index(genie_index *ix) {
+    if (!ix)
+        return;
+    int cur = 0;
+    bool sw = hipGetDevice(&cur) == hipSuccess && cur != ix->device;
+    if (sw)
+        (void)hipSetDevice(ix->device);
+    if (ix->post) (void)hipFree(ix->post);
+    if (ix->tile_base) (void)hipFree(ix->tile_base);
+    if (ix->toff) (void)hipFree(ix->toff);
+    if (sw)
+        (void)hipSetDevice(cur);
+    delete ix;
+}
+
+extern "C" int genie_index_info_get(const genie_index *ix, genie_index_info *out) {
+    clear_error();
+    if (!ix || !out) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    out->n_objects = ix->n;
+    out->n_dims = ix->d;
+    out->n_buckets = ix->V;
+    out->n_tiles = ix->n_tiles;
+    out->tile_objects = kTile;
+    out->n_postings = ix->n_postings;
+    out->device_bytes = ix->device_bytes;
+    return GENIE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// search
+// ---------------------------------------------------------------------------
+
+extern "C" size_t genie_search_workspace_size(const genie_index *ix, uint32_t n_queries,
+                                              uint32_t k) {
+    if (!ix || k == 0 || k > GENIE_MAX_K)
+        return 0;
+    return workspace_layout(ix, n_queries, k).total;
+}
+
+static int check_common(const genie_index *ix, uint32_t n_queries, uint32_t k) {
+    if (!ix) {
+        set_error("null index");
+        return GENIE_EINVAL;
+    }
+    if (k == 0 || k > GENIE_MAX_K) {
+        set_error("k=%u outside 1..%u", k, GENIE_MAX_K);
+        return GENIE_EINVAL;
+    }
+    (void)n_queries;
+    return GENIE_OK;
+}
+
+extern "C" int genie_search_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                                  const genie_item *d_items, uint64_t n_items,
+                                  uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                                  uint32_t *d_out_counts, void *d_workspace,
+                                  size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(ix, n_queries, k);
+    if (rc)
+        return rc;
+    if (n_queries == 0)
+        return GENIE_OK;
+    if (!d_q_offsets || !d_items || !d_out_ids || !d_out_counts || !d_workspace) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (max_items > GENIE_MAX_ITEMS) {
+        set_error("max_items=%u above %u", max_items, GENIE_MAX_ITEMS);
+        return GENIE_ERANGE;
+    }
+    if (((uintptr_t)d_workspace & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return GENIE_EINVAL;
+    }
+    return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, k, d_out_ids,
+                         d_out_counts, nullptr, d_workspace, workspace_bytes,
+                         (hipStream_t)stream);
+}
+
+extern "C" int genie_match_count_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                                       const genie_item *d_items, uint64_t n_items,
+                                       uint32_t n_queries,
+                                       uint32_t max_items, uint32_t *d_out_counts,
+                                       void *d_workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(ix, n_queries, 1);
+    if (rc)
+        return rc;
+    if (n_queries == 0)
+        return GENIE_OK;
+    if (!d_q_offsets || !d_items || !d_out_counts || !d_workspace) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (max_items > GENIE_MAX_ITEMS) {
+        set_error("max_items=%u above %u", max_items, GENIE_MAX_ITEMS);
+        return GENIE_ERANGE;
+    }
+    if (((uintptr_t)d_workspace & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return GENIE_EINVAL;
+    }
+    return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, 1, nullptr,
+                         nullptr, d_out_counts, d_workspace, workspace_bytes,
+                         (hipStream_t)stream);
+}
+
+namespace {
+// Device buffers of one synchronous call, freed on every exit path.
+struct DeviceBuffers {
+    std::vector<void *> ptrs;
+    ~DeviceBuffers() {
+        for (void *p : ptrs)
+            (void)hipFree(p);
+    }
+    hipError_t alloc(void **p, size_t bytes) {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 256);
+        if (e == hipSuccess)
+            ptrs.push_back(*p);
+        return e;
+    }
+};
+}  // namespace
+
+extern "C" int genie_search(const genie_index *ix, const uint64_t *q_offsets,
+                            const genie_item *items, uint32_t n_queries, uint32_t k,
+                            uint32_t *out_ids, uint32_t *out_counts) {
+    clear_error();
+    int rc = check_common(ix, n_queries, k);
+    if (rc)
+        return rc;
+    if (n_queries == 0)
+        return GENIE_OK;
+    if (!q_offsets || !out_ids || !out_counts) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (q_offsets[0] != 0) {
+        set_error("q_offsets[0] must be 0");
+        return GENIE_EINVAL;
+    }
+    uint32_t max_items = 0;
+    for (uint32_t q = 0; q < n_queries; q++) {
+        if (q_offsets[q + 1] < q_offsets[q]) {
+            set_error("q_offsets decreases at query %u", q);
+            return GENIE_EINVAL;
+        }
+        uint64_t s = q_offsets[q + 1] - q_offsets[q];
+        if (s > GENIE_MAX_ITEMS) {
+            set_error("query %u has %llu items (limit %u)", q, (unsigned long long)s,
+                      GENIE_MAX_ITEMS);
+            return GENIE_ERANGE;
+        }
+        max_items = std::max<uint32_t>(max_items, (uint32_t)s);
+    }
+    const uint64_t n_items = q_offsets[n_queries];
+    if (n_items && !items) {
+        set_error("null items");
+        return GENIE_EINVAL;
+    }
+    for (uint64_t i = 0; i < n_items; i++)
+        if (items[i].dim >= ix->d) {
+            set_error("item %llu names dim %u >= n_dims %u", (unsigned long long)i, items[i].dim,
+                      ix->d);
+            return GENIE_EINVAL;
+        }
+    SearchShape shape;
+    rc = search_shape(max_items, k, &shape);
+    if (rc)
+        return rc;
+
+    int cur = 0;
+    GENIE_HIP(hipGetDevice(&cur));
+    if (cur != ix->device)
+        GENIE_HIP(hipSetDevice(ix->device));
+    struct Restore {
+        int dev, cur;
+        ~Restore() {
+            if (dev != cur)
+                (void)hipSetDevice(cur);
+        }
+    } restore{ix->device, cur};
+
+    DeviceBuffers buf;
+    uint64_t *d_off = nullptr;
+    genie_item *d_items = nullptr;
+    uint32_t *d_ids = nullptr, *d_cts = nullptr;
+    void *d_ws = nullptr;
+    size_t ws = genie_search_workspace_size(ix, n_queries, k);
+    size_t out_bytes = (size_t)n_queries * k * sizeof(uint32_t);
+    GENIE_HIP(buf.alloc((void **)&d_off, (n_queries + 1) * sizeof(uint64_t)));
+    GENIE_HIP(buf.alloc((void **)&d_items, n_items * sizeof(genie_item)));
+    GENIE_HIP(buf.alloc((void **)&d_ids, out_bytes));
+    GENIE_HIP(buf.alloc((void **)&d_cts, out_bytes));
+    GENIE_HIP(buf.alloc(&d_ws, ws));
+    GENIE_HIP(hipMemcpy(d_off, q_offsets, (n_queries + 1) * sizeof(uint64_t),
+                        hipMemcpyHostToDevice));
+    if (n_items)
+        GENIE_HIP(hipMemcpy(d_items, items, n_items * sizeof(genie_item), hipMemcpyHostToDevice));
+    rc = launch_search(ix, d_off, d_items, n_items, n_queries, max_items, k, d_ids, d_cts,
+                       nullptr, d_ws, ws, nullptr);
+    if (rc)
+        return rc;
+    GENIE_HIP(hipDeviceSynchronize());
+    uint32_t status = 0;
+    GENIE_HIP(hipMemcpy(&status, d_ws, sizeof status, hipMemcpyDeviceToHost));
+    if (status) {
+        set_error("device status flags 0x%x", status);
+        return (status & GENIE_STATUS_TOO_MANY_ITEMS) ? GENIE_ERANGE : GENIE_EINVAL;
+    }
+    GENIE_HIP(hipMemcpy(out_ids, d_ids, out_bytes, hipMemcpyDeviceToHost));
+    GENIE_HIP(hipMemcpy(out_counts, d_cts, out_bytes, hipMemcpyDeviceToHost));
+    return GENIE_OK;
+}

@@ -1,0 +1,69 @@
+// Internal declarations of libgenie (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "genie.h"
+
+// Objects per tile.  Local ids inside a tile fit 16 bits, so postings are
+// stored as uint16 and a tile's counters fit one workgroup's LDS.
+constexpr uint32_t kTile = GENIE_TILE_OBJECTS;
+static_assert(kTile == 65536, "16-bit local ids assume 65536-object tiles");
+
+// LDS available to one workgroup on gfx950.
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+struct genie_index {
+    uint64_t n = 0;          // objects
+    uint32_t d = 0;          // dimensions
+    uint32_t V = 0;          // buckets (values) per dimension
+    uint32_t n_tiles = 0;    // ceil(n / kTile)
+    uint64_t nkeys = 0;      // d * V keywords
+    uint64_t n_postings = 0; // n * d
+    // device arrays
+    uint16_t *post = nullptr;      // tile-major, keyword-major, ascending local ids (+ pad)
+    uint64_t *tile_base = nullptr; // n_tiles + 1 element offsets of each tile in post
+    uint32_t *toff = nullptr;      // n_tiles rows of nkeys + 1 offsets, relative to tile_base
+    uint64_t device_bytes = 0;
+    int device = 0;
+};
+
+namespace genie {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+int hip_fail(hipError_t e, const char *what);
+
+#define GENIE_HIP(call)                                                      \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess)                                                \
+            return ::genie::hip_fail(e_, #call);                             \
+    } while (0)
+
+// Workspace layout of one search call (all offsets 256-byte aligned).
+struct WorkspaceLayout {
+    size_t status = 0;     // uint32 flags + pad, then uint64 stats[3]
+    size_t tile_kth = 0;   // uint32 [n_queries * n_tiles]
+    size_t cand = 0;       // uint64 [n_queries * n_tiles * k]
+    size_t total = 0;
+};
+WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint32_t k);
+
+// Counter width and table sizes picked for one search call.
+struct SearchShape {
+    int bits = 0;          // bits per packed counter
+    uint32_t ht_log2 = 0;  // hash-table slots = 1 << ht_log2
+    size_t lds_bytes = 0;  // dynamic LDS of the scan kernel
+};
+int search_shape(uint32_t max_items, uint32_t k, SearchShape *out);
+
+int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
+                  uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                  uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
+                  size_t workspace_bytes, hipStream_t stream);
+
+}  // namespace genie

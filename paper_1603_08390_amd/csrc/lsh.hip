@@ -1,0 +1,127 @@
+// LSH signatures on gfx950: the object transform of Section 4.1.2 with the
+// E2LSH family of Section 4.2.3.
+//
+//   h_i(p) = floor((a_i . p + b_i) / w)                       (float32)
+//   r_i(h) = ((A_i * u + B_i) mod 2^64) >> (64 - log2 D),      u = (uint32)h
+//
+// Each projection a_i . p is one fma chain over the coordinates in
+// ascending order, so a point's signature does not depend on which other
+// points share the launch or how the grid is cut.  A workgroup computes a
+// 64 x 64 block of (point, function) pairs from 32-coordinate slices of the
+// points and of the projection vectors staged in LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace genie {
+namespace {
+
+constexpr int kLshTile = 64;   // points and functions per workgroup
+constexpr int kLshSlice = 32;  // coordinates staged per step
+
+struct LshParams {
+    const float *points, *a, *b;
+    const uint64_t *rehash;
+    uint64_t n;
+    uint32_t dim, m, shift;
+    float w;
+    uint32_t *out;
+};
+
+__global__ __launch_bounds__(256) void lsh_kernel(LshParams p) {
+    __shared__ float ps[kLshTile][kLshSlice + 1];
+    __shared__ float as[kLshTile][kLshSlice + 1];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tx = tid & 15, ty = tid >> 4;
+    const uint32_t f0 = blockIdx.y * kLshTile;
+    const uint64_t i0 = (uint64_t)blockIdx.x * kLshTile;
+    float acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int c = 0; c < 4; c++)
+            acc[r][c] = 0.0f;
+
+    for (uint32_t j0 = 0; j0 < p.dim; j0 += kLshSlice) {
+        for (uint32_t e = tid; e < kLshTile * kLshSlice; e += 256) {
+            const uint32_t r = e / kLshSlice, c = e % kLshSlice;
+            const uint32_t j = j0 + c;
+            const uint64_t i = i0 + r;
+            const uint32_t f = f0 + r;
+            ps[r][c] = (i < p.n && j < p.dim) ? p.points[i * p.dim + j] : 0.0f;
+            as[r][c] = (f < p.m && j < p.dim) ? p.a[(uint64_t)f * p.dim + j] : 0.0f;
+        }
+        __syncthreads();
+        const uint32_t jn = min<uint32_t>(kLshSlice, p.dim - j0);
+        for (uint32_t c = 0; c < jn; c++) {
+            float pv[4], av[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                pv[r] = ps[ty * 4 + r][c];
+                av[r] = as[tx * 4 + r][c];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+#pragma unroll
+                for (int cc = 0; cc < 4; cc++)
+                    acc[r][cc] = fmaf(pv[r], av[cc], acc[r][cc]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const uint64_t i = i0 + ty * 4 + r;
+        if (i >= p.n)
+            continue;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const uint32_t f = f0 + tx * 4 + c;
+            if (f >= p.m)
+                continue;
+            const float hv = floorf((acc[r][c] + p.b[f]) / p.w);
+            // clamp to the int32 range before the conversion
+            const float lo = -2147483648.0f, hi = 2147483520.0f;
+            const int32_t h = (int32_t)fminf(fmaxf(hv, lo), hi);
+            const uint64_t u = (uint64_t)(uint32_t)h;
+            const uint64_t x = p.rehash[2 * f] * u + p.rehash[2 * f + 1];
+            p.out[i * p.m + f] = (uint32_t)(x >> p.shift);
+        }
+    }
+}
+
+}  // namespace
+}  // namespace genie
+
+using namespace genie;
+
+extern "C" int genie_lsh_signatures(const float *d_points, uint64_t n, uint32_t dim,
+                                    const float *d_a, const float *d_b, float w, uint32_t m,
+                                    const uint64_t *d_rehash, uint32_t log2_buckets,
+                                    uint32_t *d_out_sig, void *stream) {
+    clear_error();
+    if (n == 0)
+        return GENIE_OK;
+    if (!d_points || !d_a || !d_b || !d_rehash || !d_out_sig) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (dim == 0 || m == 0 || !(w > 0.0f) || !std::isfinite(w) || log2_buckets < 1 ||
+        log2_buckets > 32) {
+        set_error("bad arguments dim=%u m=%u w=%g log2_buckets=%u", dim, m, (double)w,
+                  log2_buckets);
+        return GENIE_EINVAL;
+    }
+    uint64_t gx = (n + kLshTile - 1) / kLshTile;
+    uint32_t gy = (m + kLshTile - 1) / kLshTile;
+    if (gx > 0x7FFFFFFFull || gy > 65535) {
+        set_error("too many points in one call");
+        return GENIE_EINVAL;
+    }
+    LshParams p{d_points, d_a, d_b, d_rehash, n, dim, m, 64u - log2_buckets, w, d_out_sig};
+    dim3 grid((uint32_t)gx, gy);
+    hipLaunchKernelGGL(lsh_kernel, grid, dim3(256), 0, (hipStream_t)stream, p);
+    GENIE_HIP(hipGetLastError());
+    return GENIE_OK;
+}

@@ -1,0 +1,548 @@
+// Match-count scan and count priority queue (c-PQ) on gfx950.
+//
+// One workgroup owns one (query, object tile) pair.  The tile's counters --
+// the Bitmap Counter of Section 3.3.1, b bits per object packed into 32-bit
+// LDS words -- and the Gate (ZipperArray ZA, AuditThreshold AT) and Hash
+// Table of that tile live in LDS.  The workgroup streams every posting run
+// of the query's items inside the tile (Section 3.2: scan the lists of every
+// keyword an item covers; Definition 2.1: each posting adds one), applying
+// Algorithm 1 per posting with an LDS atomic add that returns the previous
+// count.  At the end, Theorem 3.1 gives the tile's k-th count as AT - 1; the
+// tile emits its exact top-k under (count desc, id asc): the objects of
+// count >= AT found through the Hash Table, then the smallest ids of count
+// AT - 1 read from the counters (the Hash Table need not hold every tied
+// object).  A second kernel merges the per-tile lists of each query; the
+// global top-k is inside the union of the tile top-k lists because the
+// order is total.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace genie {
+namespace {
+
+struct ScanParams {
+    const uint16_t *post;
+    const uint64_t *tile_base;
+    const uint32_t *toff;
+    uint64_t n;
+    uint64_t nkeys1;        // keywords + 1 (row length of toff)
+    uint32_t d, V, n_tiles;
+    const uint64_t *q_off;
+    const uint32_t *items;  // 3 words per item
+    uint64_t n_items;       // items available at items
+    uint32_t nq, k, max_items, ht_log2;
+    uint64_t per_xcd;       // (query, tile) pairs handled per XCD slice
+    uint64_t *cand;         // [nq][n_tiles][k] packed keys
+    uint32_t *tile_kth;     // [nq][n_tiles]
+    uint32_t *full_counts;  // [nq][n] (count dump mode) or null
+    uint32_t *status;       // flags word; stats as uint64 at status + 2
+};
+
+struct MergeParams {
+    const uint64_t *cand;
+    const uint32_t *tile_kth;
+    uint32_t n_tiles, k;
+    uint32_t *out_ids, *out_counts;
+};
+
+// Answer order key: larger is better; count in the high word, then smaller
+// id.  Key 0 is the padding entry (count 0, id UINT32_MAX).
+__device__ __forceinline__ uint64_t make_key(uint32_t count, uint32_t gid) {
+    return ((uint64_t)count << 32) | (uint64_t)(0xFFFFFFFFu - gid);
+}
+
+__device__ __forceinline__ uint32_t lds_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t lds_add(uint32_t *p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t lds_or(uint32_t *p, uint32_t v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint32_t lds_max(uint32_t *p, uint32_t v) {
+    return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ bool lds_cas(uint32_t *p, uint32_t expect, uint32_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// misc words at the start of the LDS block
+enum : int { M_AT = 0, M_NABOVE = 1, M_OVERFLOW = 2, M_INSERTS = 3, M_WAVESUM = 8 };
+
+__device__ __forceinline__ uint32_t ht_home(uint32_t lid, uint32_t lg) {
+    return (lid * 2654435761u) >> (32 - lg);
+}
+
+// Hash Table insert with the modified Robin Hood scheme (Section 3.3.2).
+// Entry = count << 16 | local id (0 = empty).  Robin Hood: a probing entry
+// that is farther from its home slot than the resident takes the slot and
+// carries the resident on.  Modification: an entry whose count is below
+// AT - 1 cannot be a top-k answer any more (Theorem 3.1) and is overwritten
+// (or dropped, when carried) regardless of hashing.  The same object may end
+// up in two slots when races interleave; selection removes duplicates.
+// Returns false when the probe budget runs out (the tile then selects from
+// the counters alone, which hold every exact count).
+__device__ bool ht_insert(uint32_t *ht, uint32_t lg, uint32_t *misc, uint32_t lid, uint32_t val) {
+    const uint32_t mask = (1u << lg) - 1;
+    uint32_t entry = (val << 16) | lid;
+    uint32_t pos = ht_home(lid, lg);
+    uint32_t dist = 0;
+    for (uint32_t step = 0; step < 4u * (mask + 1) + 64; step++) {
+        const uint32_t at = lds_load(&misc[M_AT]);
+        if ((entry >> 16) + 1 < at)
+            return true;  // the carried entry has expired
+        const uint32_t cur = lds_load(&ht[pos]);
+        if (cur == 0 || (cur >> 16) + 1 < at) {
+            if (lds_cas(&ht[pos], cur, entry))
+                return true;
+            continue;  // slot changed under us: look again
+        }
+        if ((cur & 0xFFFFu) == (entry & 0xFFFFu)) {
+            if ((cur >> 16) >= (entry >> 16))
+                return true;
+            if (lds_cas(&ht[pos], cur, entry))
+                return true;
+            continue;
+        }
+        const uint32_t cdist = (pos - ht_home(cur & 0xFFFFu, lg)) & mask;
+        if (cdist < dist) {
+            if (!lds_cas(&ht[pos], cur, entry))
+                continue;
+            entry = cur;
+            dist = cdist;
+        }
+        pos = (pos + 1) & mask;
+        dist++;
+    }
+    return false;
+}
+
+// Algorithm 1 from the gate check on: HT put, ZA[val] += 1, advance AT while
+// ZA[AT] >= k.  val came from an atomic increment, so each (object, value)
+// is counted in ZA once.  A stale AT only lets extra entries in; AT never
+// passes the k-th count because ZA[v] never exceeds the objects that reached
+// v.  s is the query's item count (the largest possible count); ZA[s+1]
+// stays 0, so AT stops at s + 1 at the latest.
+__device__ void gate_pass(uint32_t *ht, uint32_t lg, uint32_t *za, uint32_t *misc, uint32_t lid,
+                          uint32_t val, uint32_t k, uint32_t s) {
+    if (!ht_insert(ht, lg, misc, lid, val))
+        misc[M_OVERFLOW] = 1;
+    lds_add(&misc[M_INSERTS], 1);
+    lds_add(&za[val], 1);
+    uint32_t a = lds_load(&misc[M_AT]);
+    while (a <= s && lds_load(&za[a]) >= k) {
+        lds_max(&misc[M_AT], a + 1);
+        a = lds_load(&misc[M_AT]);
+    }
+}
+
+// Exclusive prefix sum over the workgroup; returns the total in *total.
+template <int NT>
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32_t *total) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= (uint32_t)off)
+            incl += y;
+    }
+    if (lane == 63)
+        wave_sums[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) {
+        uint32_t ws = wave_sums[w];
+        before += (w < (int)wave) ? ws : 0;
+        all += ws;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+template <int BITS, int NT, bool DUMP>
+__global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
+    constexpr uint32_t CPW = 32 / BITS;                 // counters per word
+    constexpr uint32_t MASK = (1u << BITS) - 1;         // also the "emitted" mark
+    constexpr uint32_t NW = (kTile + CPW - 1) / CPW;    // counter words per tile
+    constexpr int U = 4;                                // dwords in flight per thread
+
+    extern __shared__ uint32_t smem[];
+    uint32_t *misc = smem;
+    uint32_t *bc = smem + 32;
+    const uint32_t lg = p.ht_log2, cap = 1u << lg;
+    uint32_t *ht = bc + NW;
+    uint32_t *za = ht + cap;
+    uint32_t *sp_off = za + (p.max_items + 2);
+    uint32_t *sp_len = sp_off + p.max_items;
+
+    // XCD-aware mapping: consecutive workgroup ids go to different XCDs, so
+    // give each XCD a contiguous range of (tile, query) pairs, tile-major,
+    // and its L2 keeps serving the same tile's postings.
+    const uint32_t bid = blockIdx.x;
+    const uint64_t pair = (uint64_t)(bid & 7) * p.per_xcd + (bid >> 3);
+    const uint64_t npairs = (uint64_t)p.nq * p.n_tiles;
+    if (pair >= npairs)
+        return;
+    const uint32_t t = (uint32_t)(pair / p.nq);
+    const uint32_t q = (uint32_t)(pair % p.nq);
+    const uint32_t tid = threadIdx.x;
+
+    const uint64_t tile0 = (uint64_t)t * kTile;
+    const uint32_t tile_n = (uint32_t)min<uint64_t>(kTile, p.n - tile0);
+    const uint64_t i0 = p.q_off[q], i1 = p.q_off[q + 1];
+    const bool bad_offsets = i1 < i0 || i1 > p.n_items;
+    const uint64_t s64 = bad_offsets ? 0 : i1 - i0;
+    const bool too_many = bad_offsets || s64 > p.max_items;
+    const uint32_t s = too_many ? 0 : (uint32_t)s64;
+
+    for (uint32_t i = tid; i < NW; i += NT)
+        bc[i] = 0;
+    for (uint32_t i = tid; i < cap; i += NT)
+        ht[i] = 0;
+    for (uint32_t i = tid; i < p.max_items + 2; i += NT)
+        za[i] = 0;
+    if (tid < 32)
+        misc[tid] = (tid == M_AT) ? 1u : 0u;
+    // Position Map lookup (Section 3.2), restricted to this tile: the keywords
+    // of one dim are adjacent, so item (dim, lo, hi) is the single run
+    // [toff[dim*V+lo], toff[dim*V+hi+1]) of the tile.
+    const uint32_t *trow = p.toff + (uint64_t)t * p.nkeys1;
+    for (uint32_t i = tid; i < s; i += NT) {
+        const uint32_t *it = p.items + 3 * (i0 + i);
+        uint32_t dim = it[0], lo = it[1], hi = it[2];
+        uint32_t b = 0, e = 0;
+        if (dim >= p.d) {
+            if (t == 0)
+                atomicOr(p.status, GENIE_STATUS_BAD_DIM);
+        } else {
+            hi = min(hi, p.V - 1);
+            if (lo <= hi) {
+                uint64_t key = (uint64_t)dim * p.V;
+                b = trow[key + lo];
+                e = trow[key + hi + 1];
+            }
+        }
+        sp_off[i] = b;
+        sp_len[i] = e - b;
+    }
+    __syncthreads();
+
+    const uint64_t row = (uint64_t)q * p.n_tiles + t;
+    if (too_many) {
+        // counts could overflow the packed width: answer with padding only
+        if (tid == 0)
+            atomicOr(p.status, bad_offsets ? GENIE_STATUS_BAD_OFFSETS : GENIE_STATUS_TOO_MANY_ITEMS);
+        if (DUMP) {
+            for (uint32_t i = tid; i < tile_n; i += NT)
+                p.full_counts[(uint64_t)q * p.n + tile0 + i] = 0;
+        } else {
+            for (uint32_t i = tid; i < p.k; i += NT)
+                p.cand[row * p.k + i] = 0;
+            if (tid == 0)
+                p.tile_kth[row] = 0;
+        }
+        return;
+    }
+
+    // ---- scan: every posting of every run adds one to its object's count
+    const uint64_t tb = p.tile_base[t];
+    const uint32_t *pw = reinterpret_cast<const uint32_t *>(p.post);
+    const uint32_t k = p.k;
+    uint32_t at_reg = 1;
+    for (uint32_t it = 0; it < s; it++) {
+        const uint32_t len = sp_len[it];
+        if (len == 0)
+            continue;
+        const uint64_t e0 = tb + sp_off[it], e1 = e0 + len;  // element range
+        const uint64_t w0 = e0 >> 1, w1 = (e1 + 1) >> 1;     // dword range
+        // Lanes of a wave take consecutive dwords (two postings each): the
+        // ids of one run ascend, so neighbouring lanes hit neighbouring
+        // counter words and LDS banks.
+        for (uint64_t w = w0 + tid; w < w1; w += (uint64_t)NT * U) {
+            uint32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint64_t ww = w + (uint64_t)u * NT;
+                v[u] = ww < w1 ? pw[ww] : 0u;
+            }
+            at_reg = lds_load(&misc[M_AT]);
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint64_t ww = w + (uint64_t)u * NT;
+                if (ww >= w1)
+                    break;
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const uint64_t el = 2 * ww + h;
+                    if (el < e0 || el >= e1)
+                        continue;
+                    const uint32_t lid = h ? (v[u] >> 16) : (v[u] & 0xFFFFu);
+                    const uint32_t word = lid / CPW;
+                    const uint32_t sh = (lid - word * CPW) * BITS;
+                    const uint32_t old = lds_add(&bc[word], 1u << sh);
+                    const uint32_t val = ((old >> sh) & MASK) + 1;
+                    if (val >= at_reg) {   // Algorithm 1: the gate check
+                        gate_pass(ht, lg, za, misc, lid, val, k, s);
+                        at_reg = lds_load(&misc[M_AT]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // settle: AT advances that raced with ZA increments are finished here
+        uint32_t a = misc[M_AT];
+        while (a <= s && za[a] >= k)
+            a++;
+        misc[M_AT] = a;
+        uint64_t scanned = 0;
+        for (uint32_t i = 0; i < s; i++)
+            scanned += sp_len[i];
+        unsigned long long *stats = reinterpret_cast<unsigned long long *>(p.status + 2);
+        atomicAdd(&stats[0], (unsigned long long)scanned);
+        if (misc[M_OVERFLOW])
+            atomicAdd(&stats[1], 1ull);
+        atomicAdd(&stats[2], (unsigned long long)misc[M_INSERTS]);
+    }
+    __syncthreads();
+
+    if (DUMP) {
+        for (uint32_t i = tid; i < tile_n; i += NT) {
+            const uint32_t word = i / CPW, sh = (i - word * CPW) * BITS;
+            p.full_counts[(uint64_t)q * p.n + tile0 + i] = (bc[word] >> sh) & MASK;
+        }
+        return;
+    }
+
+    // ---- select (Theorem 3.1): AT - 1 is the tile's k-th count
+    const uint32_t AT = misc[M_AT];
+    const uint32_t thr = AT - 1;
+    const uint32_t kk = min(k, tile_n);
+    uint64_t *out = p.cand + row * k;
+    // (1) count >= AT: fewer than k objects (Lemma 3.1), all in the HT.
+    //     Each is read back from the counters (exact) and marked emitted, so
+    //     duplicate HT slots are emitted once.
+    auto claim = [&](uint32_t lid) {
+        const uint32_t word = lid / CPW, sh = (lid - word * CPW) * BITS;
+        const uint32_t c = (lds_load(&bc[word]) >> sh) & MASK;
+        if (c == MASK || c < AT)
+            return;
+        const uint32_t old = (lds_or(&bc[word], MASK << sh) >> sh) & MASK;
+        if (old == MASK)
+            return;
+        const uint32_t pos = lds_add(&misc[M_NABOVE], 1);
+        if (pos < kk)
+            out[pos] = make_key(old, (uint32_t)(tile0 + lid));
+    };
+    if (!misc[M_OVERFLOW]) {
+        for (uint32_t slot = tid; slot < cap; slot += NT) {
+            const uint32_t cur = ht[slot];
+            if (cur != 0 && (cur & 0xFFFFu) < tile_n)
+                claim(cur & 0xFFFFu);
+        }
+    } else {
+        for (uint32_t lid = tid; lid < tile_n; lid += NT)
+            claim(lid);
+    }
+    __syncthreads();
+    const uint32_t n_above = min(misc[M_NABOVE], kk);
+    const uint32_t need = kk - n_above;
+    // (2) count == AT - 1: the smallest ids, read from the counters in id
+    //     order (a workgroup-wide prefix count over consecutive words).
+    uint32_t done = 0;
+    for (uint32_t wbase = 0; wbase < NW && done < need; wbase += NT) {
+        const uint32_t w = wbase + tid;
+        const uint32_t word = w < NW ? bc[w] : 0u;
+        uint32_t mine = 0;
+#pragma unroll
+        for (uint32_t f = 0; f < CPW; f++) {
+            const uint32_t lid = w * CPW + f;
+            mine += (w < NW && lid < tile_n && ((word >> (f * BITS)) & MASK) == thr) ? 1u : 0u;
+        }
+        uint32_t total = 0;
+        uint32_t r = done + block_exclusive_scan<NT>(mine, misc + M_WAVESUM, &total);
+        if (mine) {
+#pragma unroll
+            for (uint32_t f = 0; f < CPW; f++) {
+                const uint32_t lid = w * CPW + f;
+                if (lid < tile_n && ((word >> (f * BITS)) & MASK) == thr) {
+                    if (r < need)
+                        out[n_above + r] = make_key(thr, (uint32_t)(tile0 + lid));
+                    r++;
+                }
+            }
+        }
+        done += total;
+    }
+    for (uint32_t i = kk + tid; i < k; i += NT)
+        out[i] = 0;
+    if (tid == 0)
+        p.tile_kth[row] = thr;
+}
+
+// Per query: keep candidates whose count reaches the largest tile k-th count
+// (the global k-th count is at least that), sort them by key, emit top k.
+constexpr int kMergeBuf = 4096;   // keys held in LDS
+constexpr int kMergeChunk = 2048; // candidates read per round
+template <int NT>
+__global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
+    __shared__ uint64_t buf[kMergeBuf];
+    __shared__ uint32_t s_cnt, s_floor;
+    const uint32_t q = blockIdx.x, tid = threadIdx.x, k = p.k;
+    const uint64_t ncand = (uint64_t)p.n_tiles * k;
+    const uint64_t *cand = p.cand + (uint64_t)q * ncand;
+    if (tid == 0) {
+        s_floor = 0;
+        s_cnt = 0;
+    }
+    __syncthreads();
+    uint32_t fl = 0;
+    for (uint32_t t = tid; t < p.n_tiles; t += NT)
+        fl = max(fl, p.tile_kth[(uint64_t)q * p.n_tiles + t]);
+    atomicMax(&s_floor, fl);
+    __syncthreads();
+    const uint32_t floor_count = s_floor;
+    uint32_t kc = 0;  // valid keys at the front of buf, sorted descending
+    for (uint64_t c0 = 0; c0 < ncand; c0 += kMergeChunk) {
+        const uint64_t c1 = min<uint64_t>(ncand, c0 + kMergeChunk);
+        for (uint64_t i = c0 + tid; i < c1; i += NT) {
+            const uint64_t key = cand[i];
+            if (key != 0 && (uint32_t)(key >> 32) >= floor_count) {
+                const uint32_t pos = atomicAdd(&s_cnt, 1u);
+                buf[kc + pos] = key;
+            }
+        }
+        __syncthreads();
+        const uint32_t added = s_cnt;
+        __syncthreads();
+        if (tid == 0)
+            s_cnt = 0;
+        __syncthreads();
+        if (added == 0)
+            continue;
+        const uint32_t m = kc + added;
+        uint32_t np2 = 1;
+        while (np2 < m)
+            np2 <<= 1;
+        for (uint32_t i = m + tid; i < np2; i += NT)
+            buf[i] = 0;
+        __syncthreads();
+        // bitonic sort, descending
+        for (uint32_t size = 2; size <= np2; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t i = tid; i < np2 / 2; i += NT) {
+                    const uint32_t lo = 2 * i - (i & (stride - 1));
+                    const uint32_t hi = lo + stride;
+                    const bool desc = (lo & size) == 0;
+                    const uint64_t a = buf[lo], b = buf[hi];
+                    if ((a < b) == desc) {
+                        buf[lo] = b;
+                        buf[hi] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        kc = min(m, k);
+    }
+    for (uint32_t i = tid; i < k; i += NT) {
+        const uint64_t key = i < kc ? buf[i] : 0ull;
+        p.out_ids[(uint64_t)q * k + i] = 0xFFFFFFFFu - (uint32_t)key;
+        p.out_counts[(uint64_t)q * k + i] = (uint32_t)(key >> 32);
+    }
+}
+
+__global__ void clear_status_kernel(uint32_t *status) {
+    if (threadIdx.x < 8)
+        status[threadIdx.x] = 0;
+}
+
+template <int BITS, int NT>
+int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipStream_t st) {
+    auto kern = dump ? scan_cpq_kernel<BITS, NT, true> : scan_cpq_kernel<BITS, NT, false>;
+    GENIE_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(NT), lds, st, sp);
+    GENIE_HIP(hipGetLastError());
+    return GENIE_OK;
+}
+
+}  // namespace
+
+int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
+                  uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                  uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
+    const bool dump = d_full_counts != nullptr;
+    const WorkspaceLayout L = workspace_layout(ix, n_queries, k);
+    if (workspace_bytes < L.total) {
+        set_error("workspace of %zu bytes is smaller than the %zu needed", workspace_bytes,
+                  L.total);
+        return GENIE_EINVAL;
+    }
+    SearchShape shape;
+    int rc = search_shape(max_items, k, &shape);
+    if (rc)
+        return rc;
+    char *ws = static_cast<char *>(d_workspace);
+    ScanParams sp{};
+    sp.post = ix->post;
+    sp.tile_base = ix->tile_base;
+    sp.toff = ix->toff;
+    sp.n = ix->n;
+    sp.nkeys1 = ix->nkeys + 1;
+    sp.d = ix->d;
+    sp.V = ix->V;
+    sp.n_tiles = ix->n_tiles;
+    sp.q_off = d_q_offsets;
+    sp.items = reinterpret_cast<const uint32_t *>(d_items);
+    sp.n_items = n_items;
+    sp.nq = n_queries;
+    sp.k = k;
+    sp.max_items = max_items;
+    sp.ht_log2 = shape.ht_log2;
+    const uint64_t pairs = (uint64_t)n_queries * ix->n_tiles;
+    sp.per_xcd = (pairs + 7) / 8;
+    sp.cand = reinterpret_cast<uint64_t *>(ws + L.cand);
+    sp.tile_kth = reinterpret_cast<uint32_t *>(ws + L.tile_kth);
+    sp.full_counts = d_full_counts;
+    sp.status = reinterpret_cast<uint32_t *>(ws + L.status);
+    const uint64_t grid = sp.per_xcd * 8;
+    if (grid > 0x7FFFFFFFull) {
+        set_error("too many (query, tile) pairs in one call");
+        return GENIE_ERANGE;
+    }
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, stream, sp.status);
+    GENIE_HIP(hipGetLastError());
+    constexpr int NT = 512;
+    switch (shape.bits) {
+    case 4: rc = launch_scan<4, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 5: rc = launch_scan<5, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 6: rc = launch_scan<6, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 8: rc = launch_scan<8, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 10: rc = launch_scan<10, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 16: rc = launch_scan<16, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
+    default: set_error("no kernel for %d-bit counters", shape.bits); return GENIE_ERANGE;
+    }
+    if (rc || dump)
+        return rc;
+    MergeParams mp{};
+    mp.cand = sp.cand;
+    mp.tile_kth = sp.tile_kth;
+    mp.n_tiles = ix->n_tiles;
+    mp.k = k;
+    mp.out_ids = d_out_ids;
+    mp.out_counts = d_out_counts;
+    hipLaunchKernelGGL(merge_kernel<256>, dim3(n_queries), dim3(256), 0, stream, mp);
+    GENIE_HIP(hipGetLastError());
+    return GENIE_OK;
+}
+
+}  // namespace genie

@@ -1,0 +1,90 @@
+"""The C-ABI library loads and exports every call its header declares; the
+argument checks that need no device reject bad input.  No compute calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1603_08390_amd as genie
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "genie.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(genie_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_is_built():
+    assert os.path.exists(genie.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_every_declared_symbol_is_exported():
+    lib = genie.load()
+    names = _declared()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(genie.EXPORTED)
+
+
+def test_binding_names_match_header():
+    for name in _declared():
+        if name in ("genie_last_error", "genie_free_index", "genie_index_info_get"):
+            continue
+        assert hasattr(genie, name), name
+
+
+def test_argument_errors_without_device():
+    lib = genie.load()
+    out = ctypes.c_void_p()
+    vals = np.zeros((4, 2), dtype=np.uint32)
+    # null values / null out
+    assert lib.genie_build_index(None, 4, 2, 3, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert lib.genie_build_index(vals.ctypes.data, 4, 2, 3, None) == genie.GENIE_EINVAL
+    # zero sizes
+    assert lib.genie_build_index(vals.ctypes.data, 0, 2, 3, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert lib.genie_build_index(vals.ctypes.data, 4, 0, 3, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert lib.genie_build_index(vals.ctypes.data, 4, 2, 0, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert b"bad sizes" in lib.genie_last_error()
+    # value >= n_buckets is caught before any device call
+    bad = np.array([[0, 5]], dtype=np.uint32)
+    assert lib.genie_build_index(bad.ctypes.data, 1, 2, 3, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert b"n_buckets" in lib.genie_last_error()
+    # search on a null index, bad k
+    ids = np.zeros(4, dtype=np.uint32)
+    off = np.array([0, 0], dtype=np.uint64)
+    assert lib.genie_search(None, off.ctypes.data, None, 1, 1, ids.ctypes.data,
+                            ids.ctypes.data) == genie.GENIE_EINVAL
+    assert lib.genie_search_workspace_size(None, 1, 1) == 0
+    # LSH argument checks
+    assert lib.genie_lsh_signatures(None, 10, 4, None, None, ctypes.c_float(1.0), 3, None, 13,
+                                    None, None) == genie.GENIE_EINVAL
+    # n = 0 is a no-op
+    assert lib.genie_lsh_signatures(None, 0, 4, None, None, ctypes.c_float(1.0), 3, None, 13,
+                                    None, None) == genie.GENIE_OK
+
+
+def test_header_limits_match_binding():
+    text = open(HEADER).read()
+    for name, val in (("GENIE_MAX_K", genie.GENIE_MAX_K), ("GENIE_MAX_ITEMS", genie.GENIE_MAX_ITEMS),
+                      ("GENIE_TILE_OBJECTS", genie.GENIE_TILE_OBJECTS),
+                      ("GENIE_EINVAL", genie.GENIE_EINVAL), ("GENIE_ERANGE", genie.GENIE_ERANGE)):
+        m = re.search(r"#define\s+%s\s+\(?(-?\d+)" % name, text)
+        assert m and int(m.group(1)) == val, name
+
+
+def test_oracle_shares_no_code_with_library():
+    """The oracle's sources name nothing from the GPU library and the
+    library's sources name nothing from the oracle."""
+    osrc = open(os.path.join(ROOT, "oracle", "genie_oracle.c")).read()
+    opy = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+    assert "genie.h" not in osrc and "paper_1603_08390_amd" not in opy
+    csrc = os.path.join(ROOT, "paper_1603_08390_amd", "csrc")
+    for f in os.listdir(csrc):
+        assert "oracle" not in open(os.path.join(csrc, f)).read().lower(), f
+    assert "oracle" not in open(os.path.join(ROOT, "paper_1603_08390_amd", "__init__.py")).read()
