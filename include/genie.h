@@ -54,7 +54,7 @@ extern "C" {
 /* Limits of one search call. */
 #define GENIE_MAX_K 1024          /* results per query */
 #define GENIE_MAX_ITEMS 1024      /* items per query (bounds the count) */
-#define GENIE_TILE_OBJECTS 65536  /* objects per index tile (16-bit local ids) */
+#define GENIE_TILE_OBJECTS 65535  /* objects per index tile (16-bit local ids, 0xFFFF reserved) */
 
 /* Device status flags, OR-ed into the first word of a search workspace. */
 #define GENIE_STATUS_BAD_DIM 1u       /* an item named dim >= n_dims (treated as empty) */
@@ -93,7 +93,8 @@ typedef struct {
  * Layout on the device: objects are cut into tiles of GENIE_TILE_OBJECTS;
  * postings are stored tile-major, then keyword-major, as 16-bit ids local to
  * the tile in ascending order, so that every keyword list restricted to a
- * tile is one contiguous run and the runs of one dimension are adjacent.
+ * tile is one contiguous run and the runs of one dimension are adjacent;
+ * each run is padded to an even length with the reserved id 0xFFFF.
  * Errors: GENIE_EINVAL (null pointer, size, value >= n_buckets),
  * GENIE_ENOMEM, GENIE_EDEVICE.
  */
@@ -142,10 +143,11 @@ size_t genie_search_workspace_size(const genie_index *ix, uint32_t n_queries, ui
  *   d_workspace: device, >= genie_search_workspace_size(ix, n_queries, k)
  *                bytes, 256-byte aligned.  After the stream passes the call,
  *                its first uint32 holds the OR of GENIE_STATUS_* flags, and
- *                the following uint64 words hold: postings scanned, tiles whose
- *                hash table overflowed (answered exactly from the counters),
- *                hash-table insertions.  Calls that share a workspace must be
- *                ordered on one stream.
+ *                the uint64 words at byte offsets 8, 16, 24 and 32 hold:
+ *                postings scanned, tiles whose hash table overflowed (answered
+ *                exactly from the counters), hash-table insertions, and
+ *                increments that passed the gate.  Calls that share a
+ *                workspace must be ordered on one stream.
  *   stream:      hipStream_t or NULL.
  * Host-side checks only (k, max_items, pointers); item contents are checked
  * on the device (bad dims flag GENIE_STATUS_BAD_DIM and act as empty items).
@@ -186,6 +188,23 @@ int genie_match_count_async(const genie_index *ix, const uint64_t *d_q_offsets,
 int genie_lsh_signatures(const float *d_points, uint64_t n, uint32_t dim, const float *d_a,
                          const float *d_b, float w, uint32_t m, const uint64_t *d_rehash,
                          uint32_t log2_buckets, uint32_t *d_out_sig, void *stream);
+
+/*
+ * Per-kernel timing for measurement.  While enabled, every search call
+ * records a HIP event pair around its scan kernel and around its merge
+ * kernel, on the stream of the call.  genie_kernel_timing_read waits for the
+ * recorded events, adds up their elapsed times and (if reset != 0) clears the
+ * totals.  Disabled by default; process-wide; thread-safe.
+ */
+typedef struct {
+    uint64_t scan_launches;
+    double scan_ms;      /* summed event time of the scan + c-PQ kernel */
+    uint64_t merge_launches;
+    double merge_ms;     /* summed event time of the per-query merge kernel */
+} genie_kernel_times;
+
+int genie_kernel_timing_enable(int on);
+int genie_kernel_timing_read(genie_kernel_times *out, int reset);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *genie_last_error(void);

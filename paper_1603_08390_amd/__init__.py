@@ -19,7 +19,7 @@ from typing import Optional, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgenie.so")
+LIB_PATH = os.environ.get("GENIE_LIB", os.path.join(HERE, "libgenie.so"))
 
 GENIE_OK = 0
 GENIE_EINVAL = -22
@@ -28,7 +28,7 @@ GENIE_EDEVICE = -5
 GENIE_ERANGE = -34
 GENIE_MAX_K = 1024
 GENIE_MAX_ITEMS = 1024
-GENIE_TILE_OBJECTS = 65536
+GENIE_TILE_OBJECTS = 65535
 STATUS_BAD_DIM = 1
 STATUS_TOO_MANY_ITEMS = 2
 STATUS_BAD_OFFSETS = 4
@@ -36,7 +36,8 @@ STATUS_BAD_OFFSETS = 4
 EXPORTED = (
     "genie_build_index", "genie_free_index", "genie_index_info_get", "genie_search",
     "genie_search_workspace_size", "genie_search_async", "genie_match_count_async",
-    "genie_lsh_signatures", "genie_last_error",
+    "genie_lsh_signatures", "genie_last_error", "genie_kernel_timing_enable",
+    "genie_kernel_timing_read",
 )
 
 
@@ -44,6 +45,11 @@ class GenieError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libgenie error {code}: {msg}")
         self.code = code
+
+
+class _KernelTimes(ctypes.Structure):
+    _fields_ = [("scan_launches", ctypes.c_uint64), ("scan_ms", ctypes.c_double),
+                ("merge_launches", ctypes.c_uint64), ("merge_ms", ctypes.c_double)]
 
 
 class _IndexInfo(ctypes.Structure):
@@ -83,6 +89,10 @@ def load() -> ctypes.CDLL:
     lib.genie_lsh_signatures.argtypes = [vp, u64, u32, vp, vp, ctypes.c_float, u32, vp, u32,
                                          vp, vp]
     lib.genie_lsh_signatures.restype = ctypes.c_int
+    lib.genie_kernel_timing_enable.argtypes = [ctypes.c_int]
+    lib.genie_kernel_timing_enable.restype = ctypes.c_int
+    lib.genie_kernel_timing_read.argtypes = [ctypes.POINTER(_KernelTimes), ctypes.c_int]
+    lib.genie_kernel_timing_read.restype = ctypes.c_int
     lib.genie_last_error.argtypes = []
     lib.genie_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -249,13 +259,25 @@ def genie_lsh_signatures(d_points, d_a, d_b, w: float, d_rehash, log2_buckets: i
     return out
 
 
+def genie_kernel_timing_enable(on: bool = True):
+    _check(load().genie_kernel_timing_enable(1 if on else 0))
+
+
+def genie_kernel_timing_read(reset: bool = True) -> dict:
+    t = _KernelTimes()
+    _check(load().genie_kernel_timing_read(ctypes.byref(t), 1 if reset else 0))
+    return {"scan_launches": t.scan_launches, "scan_ms": t.scan_ms,
+            "merge_launches": t.merge_launches, "merge_ms": t.merge_ms}
+
+
 def workspace_stats(workspace) -> dict:
     """Status flags and counters left in a workspace by the last search."""
-    head = workspace[:32].cpu().numpy()
+    head = workspace[:40].cpu().numpy()
     status = int(head[:4].view(np.uint32)[0])
-    stats = head[8:32].view(np.uint64)
+    stats = head[8:40].view(np.uint64)
     return {"status": status, "postings_scanned": int(stats[0]),
-            "ht_overflow_tiles": int(stats[1]), "ht_inserts": int(stats[2])}
+            "ht_overflow_tiles": int(stats[1]), "ht_inserts": int(stats[2]),
+            "gate_passes": int(stats[3])}
 
 
 def queries_to_device(q_offsets: np.ndarray, items: np.ndarray, device="cuda"):

@@ -47,7 +47,7 @@ WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint
 int search_shape(uint32_t max_items, uint32_t k, SearchShape *out) {
     // Counter width b: counts reach at most max_items; one more code (all
     // ones) marks an object already emitted during selection.
-    static const int widths[] = {4, 5, 6, 8, 10, 16};
+    static const int widths[] = {4, 8, 16};
     int bits = 0;
     for (int b : widths)
         if ((uint64_t)max_items + 2 <= (1ull << b)) {
@@ -63,14 +63,18 @@ int search_shape(uint32_t max_items, uint32_t k, SearchShape *out) {
     uint32_t lg = 6;
     while ((1u << lg) < 4u * k)
         lg++;
-    uint32_t cpw = 32 / bits;
-    size_t words = 32 + (kTile + cpw - 1) / cpw + (1u << lg) + (max_items + 2) + 2ull * max_items;
+    const uint32_t cpw = 32 / bits;
+    // static part: the Bitmap Counter (a counter for every 16-bit id)
+    const size_t bc_words = 65536 / cpw;
+    // dynamic part: misc, HT, ZA, run table, gate queues
+    size_t words = 32 + (1u << lg) + (max_items + 2) + 2ull * max_items + 1 +
+                   (size_t)(kScanThreads / 64) * kGateQueue;
     out->bits = bits;
     out->ht_log2 = lg;
     out->lds_bytes = words * 4;
-    if (out->lds_bytes > kMaxLdsBytes) {
+    if ((bc_words + words) * 4 > kMaxLdsBytes) {
         set_error("search needs %zu bytes of LDS (k=%u, max_items=%u); limit %zu",
-                  out->lds_bytes, k, max_items, kMaxLdsBytes);
+                  (bc_words + words) * 4, k, max_items, kMaxLdsBytes);
         return GENIE_ERANGE;
     }
     return GENIE_OK;
@@ -94,34 +98,35 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
         return GENIE_EINVAL;
     }
     *out = nullptr;
-    if (n == 0 || n >= 0xFFFFFFFFull || d == 0 || V == 0 || (uint64_t)d * V >= 0xFFFFFFFFull ||
-        (uint64_t)kTile * d >= 0xFFFFFFFFull) {
+    if (n == 0 || n >= 0xFFFFFFFFull || d == 0 || V == 0 || (uint64_t)d * V >= 0xFFFFFFFFull) {
         set_error("bad sizes n=%llu d=%u V=%u", (unsigned long long)n, d, V);
         return GENIE_EINVAL;
     }
     const uint32_t T = (uint32_t)((n + kTile - 1) / kTile);
     const uint64_t nkeys = (uint64_t)d * V;
     const uint64_t npost = n * d;
-    const uint64_t pad = 64;  // aligned dword loads may touch one element past a run
+    if ((uint64_t)kTile * d + nkeys >= 0xFFFFFFFFull) {
+        set_error("n_dims * n_buckets too large for 32-bit tile offsets");
+        return GENIE_EINVAL;
+    }
 
+    // Per tile: run length of every keyword (counting sort), each run padded
+    // to an even number of elements with the sentinel id kSentinel so that
+    // runs start and end on dword boundaries.  toff = padded offsets, tpad =
+    // number of padded runs before each keyword (to recover real lengths).
     std::vector<uint32_t> toff((uint64_t)T * (nkeys + 1));
-    std::vector<uint64_t> tile_base(T + 1);
-    std::vector<uint16_t> post(npost + pad, 0);
-    for (uint32_t t = 0; t <= T; t++)
-        tile_base[t] = std::min<uint64_t>((uint64_t)t * kTile, n) * d;
-
-    // Counting sort per tile, by keyword; objects visited in ascending id
-    // order so that every run is ascending.
+    std::vector<uint32_t> tpad((uint64_t)T * (nkeys + 1));
+    std::vector<uint64_t> tile_size(T), tile_base(T + 1);
     std::atomic<int> bad{0};
     std::atomic<uint32_t> next{0};
-    auto worker = [&]() {
-        std::vector<uint32_t> fill(nkeys);
+    auto count_tiles = [&]() {
         for (;;) {
             uint32_t t = next.fetch_add(1);
             if (t >= T)
                 break;
             uint64_t o0 = (uint64_t)t * kTile, o1 = std::min<uint64_t>(o0 + kTile, n);
             uint32_t *row = &toff[(uint64_t)t * (nkeys + 1)];
+            uint32_t *prow = &tpad[(uint64_t)t * (nkeys + 1)];
             for (uint64_t o = o0; o < o1; o++)
                 for (uint32_t j = 0; j < d; j++) {
                     uint32_t v = values[o * d + j];
@@ -131,10 +136,48 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
                     }
                     row[(uint64_t)j * V + v + 1]++;
                 }
-            for (uint64_t key = 0; key < nkeys; key++)
-                row[key + 1] += row[key];
-            std::memcpy(fill.data(), row, nkeys * sizeof(uint32_t));
+            uint32_t off = 0, pads = 0;
+            row[0] = 0;
+            prow[0] = 0;
+            for (uint64_t key = 0; key < nkeys; key++) {
+                uint32_t len = row[key + 1];
+                off += len + (len & 1u);
+                pads += len & 1u;
+                row[key + 1] = off;
+                prow[key + 1] = pads;
+            }
+            tile_size[t] = off + 2 * kSentinelDwords;   // trailing all-sentinel dwords
+        }
+    };
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, T);
+    {
+        std::vector<std::thread> pool;
+        for (unsigned i = 0; i < nth; i++)
+            pool.emplace_back(count_tiles);
+        for (auto &th : pool)
+            th.join();
+    }
+    if (bad.load()) {
+        set_error("a value is >= n_buckets (%u)", V);
+        return GENIE_EINVAL;
+    }
+    tile_base[0] = 0;
+    for (uint32_t t = 0; t < T; t++)
+        tile_base[t + 1] = tile_base[t] + tile_size[t];
+    const uint64_t stored = tile_base[T];
+    std::vector<uint16_t> post(stored, kSentinel);
+    next.store(0);
+    auto fill_tiles = [&]() {
+        std::vector<uint32_t> fill(nkeys);
+        for (;;) {
+            uint32_t t = next.fetch_add(1);
+            if (t >= T)
+                break;
+            uint64_t o0 = (uint64_t)t * kTile, o1 = std::min<uint64_t>(o0 + kTile, n);
+            std::memcpy(fill.data(), &toff[(uint64_t)t * (nkeys + 1)], nkeys * sizeof(uint32_t));
             uint16_t *dst = &post[tile_base[t]];
+            // objects in ascending id order: every run ascends
             for (uint64_t o = o0; o < o1; o++)
                 for (uint32_t j = 0; j < d; j++) {
                     uint64_t key = (uint64_t)j * V + values[o * d + j];
@@ -142,16 +185,12 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
                 }
         }
     };
-    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    nth = std::min<unsigned>(nth, T);
-    std::vector<std::thread> pool;
-    for (unsigned i = 0; i < nth; i++)
-        pool.emplace_back(worker);
-    for (auto &th : pool)
-        th.join();
-    if (bad.load()) {
-        set_error("a value is >= n_buckets (%u)", V);
-        return GENIE_EINVAL;
+    {
+        std::vector<std::thread> pool;
+        for (unsigned i = 0; i < nth; i++)
+            pool.emplace_back(fill_tiles);
+        for (auto &th : pool)
+            th.join();
     }
 
     genie_index *ix = new (std::nothrow) genie_index;
@@ -165,21 +204,24 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
     ix->n_tiles = T;
     ix->nkeys = nkeys;
     ix->n_postings = npost;
+    ix->stored_postings = stored;
     hipError_t e = hipGetDevice(&ix->device);
     size_t bp = post.size() * sizeof(uint16_t), bb = tile_base.size() * sizeof(uint64_t),
            bt = toff.size() * sizeof(uint32_t);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->post, bp);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->tile_base, bb);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->toff, bt);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->tpad, bt);
     if (e == hipSuccess) e = hipMemcpy(ix->post, post.data(), bp, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->tile_base, tile_base.data(), bb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->toff, toff.data(), bt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ix->tpad, tpad.data(), bt, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         int rc = hip_fail(e, "index upload");
         genie_free_index(ix);
         return rc;
     }
-    ix->device_bytes = bp + bb + bt;
+    ix->device_bytes = bp + bb + 2 * bt;
     *out = ix;
     return GENIE_OK;
 }
@@ -194,6 +236,7 @@ extern "C" void genie_free_index(genie_index *ix) {
     if (ix->post) (void)hipFree(ix->post);
     if (ix->tile_base) (void)hipFree(ix->tile_base);
     if (ix->toff) (void)hipFree(ix->toff);
+    if (ix->tpad) (void)hipFree(ix->tpad);
     if (sw)
         (void)hipSetDevice(cur);
     delete ix;

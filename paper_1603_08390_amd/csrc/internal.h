@@ -9,12 +9,32 @@
 #include "genie.h"
 
 // Objects per tile.  Local ids inside a tile fit 16 bits, so postings are
-// stored as uint16 and a tile's counters fit one workgroup's LDS.
+// stored as uint16 and a tile's counters fit one workgroup's LDS.  The id
+// 0xFFFF is never an object: it pads keyword runs to an even length.
 constexpr uint32_t kTile = GENIE_TILE_OBJECTS;
-static_assert(kTile == 65536, "16-bit local ids assume 65536-object tiles");
+static_assert(kTile == 65535, "16-bit local ids with 0xFFFF reserved");
+constexpr uint16_t kSentinel = 0xFFFF;
+constexpr uint64_t kSentinelDwords = 64;   // all-sentinel dwords after each tile's runs
 
 // LDS available to one workgroup on gfx950.
 constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+// Scan kernel launch shape: threads per workgroup (at least 512: the run
+// table prefix sum gives each thread two of at most 1024 runs) and posting
+// dwords each thread loads per step.
+#ifndef GENIE_SCAN_THREADS
+#define GENIE_SCAN_THREADS 512
+#endif
+#ifndef GENIE_SCAN_UNROLL
+#define GENIE_SCAN_UNROLL 8
+#endif
+constexpr int kScanThreads = GENIE_SCAN_THREADS;
+// Gate queue entries per wave (LDS words): fewer than 64 wait between
+// rounds, and one posting slot adds at most 64.
+constexpr uint32_t kGateQueue = 128;
+constexpr int kScanUnroll = GENIE_SCAN_UNROLL;
+static_assert(kScanThreads >= 512 && kScanThreads <= 1024 && kScanThreads % 64 == 0,
+              "scan workgroup size");
 
 struct genie_index {
     uint64_t n = 0;          // objects
@@ -26,7 +46,9 @@ struct genie_index {
     // device arrays
     uint16_t *post = nullptr;      // tile-major, keyword-major, ascending local ids (+ pad)
     uint64_t *tile_base = nullptr; // n_tiles + 1 element offsets of each tile in post
-    uint32_t *toff = nullptr;      // n_tiles rows of nkeys + 1 offsets, relative to tile_base
+    uint32_t *toff = nullptr;      // n_tiles rows of nkeys + 1 padded offsets, relative to tile_base
+    uint32_t *tpad = nullptr;      // n_tiles rows of nkeys + 1 counts of padded runs before a keyword
+    uint64_t stored_postings = 0;  // elements in post (real + padding + trailing sentinels)
     uint64_t device_bytes = 0;
     int device = 0;
 };
@@ -57,7 +79,7 @@ WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint
 struct SearchShape {
     int bits = 0;          // bits per packed counter
     uint32_t ht_log2 = 0;  // hash-table slots = 1 << ht_log2
-    size_t lds_bytes = 0;  // dynamic LDS of the scan kernel
+    size_t lds_bytes = 0;  // dynamic LDS of the scan kernel (the counters are static)
 };
 int search_shape(uint32_t max_items, uint32_t k, SearchShape *out);
 
@@ -65,5 +87,9 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
                   size_t workspace_bytes, hipStream_t stream);
+
+// Opt-in kernel timing (timing.cpp): begin returns an event handle or null.
+void *timing_begin(hipStream_t st);
+void timing_end(void *start, hipStream_t st, int kind);
 
 }  // namespace genie

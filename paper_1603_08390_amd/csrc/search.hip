@@ -25,6 +25,7 @@ struct ScanParams {
     const uint16_t *post;
     const uint64_t *tile_base;
     const uint32_t *toff;
+    const uint32_t *tpad;
     uint64_t n;
     uint64_t nkeys1;        // keywords + 1 (row length of toff)
     uint32_t d, V, n_tiles;
@@ -70,7 +71,10 @@ __device__ __forceinline__ bool lds_cas(uint32_t *p, uint32_t expect, uint32_t d
 }
 
 // misc words at the start of the LDS block
-enum : int { M_AT = 0, M_NABOVE = 1, M_OVERFLOW = 2, M_INSERTS = 3, M_WAVESUM = 8 };
+enum : int {
+    M_AT = 0, M_NABOVE = 1, M_OVERFLOW = 2, M_INSERTS = 3, M_SCANNED = 4, M_PASSES = 5,
+    M_WAVESUM = 8
+};
 
 __device__ __forceinline__ uint32_t ht_home(uint32_t lid, uint32_t lg) {
     return (lid * 2654435761u) >> (32 - lg);
@@ -79,23 +83,26 @@ __device__ __forceinline__ uint32_t ht_home(uint32_t lid, uint32_t lg) {
 // Hash Table insert with the modified Robin Hood scheme (Section 3.3.2).
 // Entry = count << 16 | local id (0 = empty).  Robin Hood: a probing entry
 // that is farther from its home slot than the resident takes the slot and
-// carries the resident on.  Modification: an entry whose count is below
-// AT - 1 cannot be a top-k answer any more (Theorem 3.1) and is overwritten
-// (or dropped, when carried) regardless of hashing.  The same object may end
-// up in two slots when races interleave; selection removes duplicates.
-// Returns false when the probe budget runs out (the tile then selects from
-// the counters alone, which hold every exact count).
+// carries the resident on.  Modification: an entry that can no longer be
+// among the objects of count >= AT is overwritten (or dropped, when carried)
+// regardless of hashing.  The paper expires entries below AT - 1; here the
+// objects tied at AT - 1 are taken from the exact counters at selection
+// time, so the table only has to keep entries of count >= AT and expires
+// everything below AT.  The same object may end up in two slots when races
+// interleave; selection removes duplicates.  Returns false when a full sweep
+// finds no free slot (the tile then selects from the counters alone, which
+// hold every exact count).
 __device__ bool ht_insert(uint32_t *ht, uint32_t lg, uint32_t *misc, uint32_t lid, uint32_t val) {
     const uint32_t mask = (1u << lg) - 1;
     uint32_t entry = (val << 16) | lid;
     uint32_t pos = ht_home(lid, lg);
     uint32_t dist = 0;
-    for (uint32_t step = 0; step < 4u * (mask + 1) + 64; step++) {
+    for (uint32_t step = 0; step < 2u * (mask + 1) + 16; step++) {
         const uint32_t at = lds_load(&misc[M_AT]);
-        if ((entry >> 16) + 1 < at)
+        if ((entry >> 16) < at)
             return true;  // the carried entry has expired
         const uint32_t cur = lds_load(&ht[pos]);
-        if (cur == 0 || (cur >> 16) + 1 < at) {
+        if (cur == 0 || (cur >> 16) < at) {
             if (lds_cas(&ht[pos], cur, entry))
                 return true;
             continue;  // slot changed under us: look again
@@ -120,22 +127,30 @@ __device__ bool ht_insert(uint32_t *ht, uint32_t lg, uint32_t *misc, uint32_t li
     return false;
 }
 
-// Algorithm 1 from the gate check on: HT put, ZA[val] += 1, advance AT while
-// ZA[AT] >= k.  val came from an atomic increment, so each (object, value)
-// is counted in ZA once.  A stale AT only lets extra entries in; AT never
-// passes the k-th count because ZA[v] never exceeds the objects that reached
-// v.  s is the query's item count (the largest possible count); ZA[s+1]
-// stays 0, so AT stops at s + 1 at the latest.
-__device__ void gate_pass(uint32_t *ht, uint32_t lg, uint32_t *za, uint32_t *misc, uint32_t lid,
-                          uint32_t val, uint32_t k, uint32_t s) {
-    if (!ht_insert(ht, lg, misc, lid, val))
-        misc[M_OVERFLOW] = 1;
-    lds_add(&misc[M_INSERTS], 1);
-    lds_add(&za[val], 1);
+// Algorithm 1 after the gate check, part 1: advance AT while ZA[AT] >= k
+// (the caller has just added to ZA).  A stale AT only lets extra increments
+// through the gate; AT never passes the k-th count because ZA[v] never
+// exceeds the objects that reached v (each (object, value) pair is counted
+// once: val comes from an atomic increment).  s is the query's item count
+// (the largest possible count); ZA[s+1] stays 0, so AT stops at s + 1.
+__device__ void advance_at(uint32_t *za, uint32_t *misc, uint32_t k, uint32_t s) {
     uint32_t a = lds_load(&misc[M_AT]);
     while (a <= s && lds_load(&za[a]) >= k) {
         lds_max(&misc[M_AT], a + 1);
         a = lds_load(&misc[M_AT]);
+    }
+}
+
+// Algorithm 1, part 2: put (object, val) into the HT.  Callers run it some
+// time after the increment (queued per wave); an increment that AT has left
+// behind by then (val < AT) is not stored, which keeps the table small.
+// Every object whose final count reaches the final AT is stored by its last
+// increment, because AT never exceeds its final value.
+__device__ void ht_put(uint32_t *ht, uint32_t lg, uint32_t *misc, uint32_t lid, uint32_t val) {
+    if (val >= lds_load(&misc[M_AT]) && lds_load(&misc[M_OVERFLOW]) == 0) {
+        lds_add(&misc[M_INSERTS], 1);
+        if (!ht_insert(ht, lg, misc, lid, val))
+            misc[M_OVERFLOW] = 1;
     }
 }
 
@@ -165,21 +180,31 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32
     return before + incl - v;
 }
 
-template <int BITS, int NT, bool DUMP>
+template <int BITS, int NT, int U, bool DUMP>
 __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
-    constexpr uint32_t CPW = 32 / BITS;                 // counters per word
-    constexpr uint32_t MASK = (1u << BITS) - 1;         // also the "emitted" mark
-    constexpr uint32_t NW = (kTile + CPW - 1) / CPW;    // counter words per tile
-    constexpr int U = 4;                                // dwords in flight per thread
+    static_assert(BITS == 4 || BITS == 8 || BITS == 16, "power-of-two counter width");
+    constexpr uint32_t CPW = 32 / BITS;                   // counters per word
+    constexpr uint32_t LCPW = BITS == 4 ? 3 : (BITS == 8 ? 2 : 1);   // log2(CPW)
+    constexpr uint32_t LBITS = BITS == 4 ? 2 : (BITS == 8 ? 3 : 4);  // log2(BITS)
+    constexpr uint32_t MASK = (1u << BITS) - 1;           // also the "emitted" mark
+    constexpr uint32_t NW = 65536 / CPW;                  // a counter for every 16-bit id
+    constexpr uint32_t NWAVE = NT / 64;
+    constexpr uint32_t CH = 64 * U;                       // dwords per wave per step
 
+    // The Bitmap Counter has a fixed size per counter width; as a static
+    // array at LDS offset 0 its addresses need no base register.
+    __shared__ uint32_t bc[NW];
     extern __shared__ uint32_t smem[];
     uint32_t *misc = smem;
-    uint32_t *bc = smem + 32;
     const uint32_t lg = p.ht_log2, cap = 1u << lg;
-    uint32_t *ht = bc + NW;
+    uint32_t *ht = smem + 32;
     uint32_t *za = ht + cap;
-    uint32_t *sp_off = za + (p.max_items + 2);
-    uint32_t *sp_len = sp_off + p.max_items;
+    // run table: first dword of each item's run (tile-relative) and the
+    // prefix counts of the runs' dwords
+    uint32_t *sp_dw = za + (p.max_items + 2);
+    uint32_t *sp_cum = sp_dw + p.max_items;               // max_items + 1 entries
+    // per-wave queue of (count << 16 | local id) pairs that passed the gate
+    uint32_t *gq = sp_cum + p.max_items + 1 + ((threadIdx.x >> 6) * kGateQueue);
 
     // XCD-aware mapping: consecutive workgroup ids go to different XCDs, so
     // give each XCD a contiguous range of (tile, query) pairs, tile-major,
@@ -209,27 +234,45 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
         za[i] = 0;
     if (tid < 32)
         misc[tid] = (tid == M_AT) ? 1u : 0u;
+    __syncthreads();
     // Position Map lookup (Section 3.2), restricted to this tile: the keywords
     // of one dim are adjacent, so item (dim, lo, hi) is the single run
-    // [toff[dim*V+lo], toff[dim*V+hi+1]) of the tile.
+    // [toff[dim*V+lo], toff[dim*V+hi+1]) of the tile (padded to whole dwords).
     const uint32_t *trow = p.toff + (uint64_t)t * p.nkeys1;
+    const uint32_t *prow = p.tpad + (uint64_t)t * p.nkeys1;
     for (uint32_t i = tid; i < s; i += NT) {
         const uint32_t *it = p.items + 3 * (i0 + i);
         uint32_t dim = it[0], lo = it[1], hi = it[2];
-        uint32_t b = 0, e = 0;
+        uint32_t b = 0, e = 0, pads = 0;
         if (dim >= p.d) {
             if (t == 0)
                 atomicOr(p.status, GENIE_STATUS_BAD_DIM);
         } else {
             hi = min(hi, p.V - 1);
             if (lo <= hi) {
-                uint64_t key = (uint64_t)dim * p.V;
+                const uint64_t key = (uint64_t)dim * p.V;
                 b = trow[key + lo];
                 e = trow[key + hi + 1];
+                pads = prow[key + hi + 1] - prow[key + lo];
             }
         }
-        sp_off[i] = b;
-        sp_len[i] = e - b;
+        sp_dw[i] = b >> 1;
+        sp_cum[i] = (e - b) >> 1;   // dwords of the run (temporary)
+        lds_add(&misc[M_SCANNED], (e - b) - pads);
+    }
+    __syncthreads();
+    // prefix counts of the runs' dwords (at most 1024 runs, 2 per thread)
+    {
+        const uint32_t a0 = 2 * tid, a1 = 2 * tid + 1;
+        const uint32_t c0 = a0 < s ? sp_cum[a0] : 0u, c1 = a1 < s ? sp_cum[a1] : 0u;
+        uint32_t total = 0;
+        const uint32_t ex = block_exclusive_scan<NT>(c0 + c1, misc + M_WAVESUM, &total);
+        if (a0 < s)
+            sp_cum[a0] = ex;
+        if (a1 < s)
+            sp_cum[a1] = ex + c0;
+        if (tid == 0)
+            sp_cum[s] = total;
     }
     __syncthreads();
 
@@ -250,51 +293,135 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
         return;
     }
 
-    // ---- scan: every posting of every run adds one to its object's count
-    const uint64_t tb = p.tile_base[t];
-    const uint32_t *pw = reinterpret_cast<const uint32_t *>(p.post);
+    // ---- scan: every posting of every run adds one to its object's count.
+    // The runs' dwords form one stream cut into 64-dword pieces; lane l of a
+    // wave takes dword l of a piece (two postings), so the ids that
+    // neighbouring lanes touch ascend together and spread over neighbouring
+    // LDS banks.  The run cursor is the same in every lane: a piece inside
+    // one run is addressed as cursor + lane.  Runs are padded with the
+    // reserved id 0xFFFF, whose counter is a dummy (the top field of the
+    // last word, where carries fall off), so every element is counted
+    // without a bounds test; lanes past the end read the tile's trailing
+    // all-sentinel dwords.
+    const char *tile_bytes = reinterpret_cast<const char *>(p.post) + 2 * p.tile_base[t];
+    const uint32_t sent_dw = trow[p.nkeys1 - 1] >> 1;   // trailing sentinel dwords of the tile
     const uint32_t k = p.k;
-    uint32_t at_reg = 1;
-    for (uint32_t it = 0; it < s; it++) {
-        const uint32_t len = sp_len[it];
-        if (len == 0)
-            continue;
-        const uint64_t e0 = tb + sp_off[it], e1 = e0 + len;  // element range
-        const uint64_t w0 = e0 >> 1, w1 = (e1 + 1) >> 1;     // dword range
-        // Lanes of a wave take consecutive dwords (two postings each): the
-        // ids of one run ascend, so neighbouring lanes hit neighbouring
-        // counter words and LDS banks.
-        for (uint64_t w = w0 + tid; w < w1; w += (uint64_t)NT * U) {
-            uint32_t v[U];
+    // wave-uniform values, so that the run cursor lives in scalar registers
+    const uint32_t total_dw = __builtin_amdgcn_readfirstlane(sp_cum[s]);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    uint32_t qn = 0;       // pairs in this wave's gate queue (same in every lane)
+    uint32_t passes = 0;   // increments this wave let through the gate
+    uint32_t si = 0, c_lo = 0;
+    uint32_t c_hi = s ? __builtin_amdgcn_readfirstlane(sp_cum[1]) : 0u;
+    uint32_t dwb = s ? __builtin_amdgcn_readfirstlane(sp_dw[0]) : 0u;
+    for (uint32_t cb = wave * CH; cb < total_dw; cb += NWAVE * CH) {
+        uint32_t off[U];
 #pragma unroll
-            for (int u = 0; u < U; u++) {
-                const uint64_t ww = w + (uint64_t)u * NT;
-                v[u] = ww < w1 ? pw[ww] : 0u;
-            }
-            at_reg = lds_load(&misc[M_AT]);
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const uint64_t ww = w + (uint64_t)u * NT;
-                if (ww >= w1)
-                    break;
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const uint64_t el = 2 * ww + h;
-                    if (el < e0 || el >= e1)
-                        continue;
-                    const uint32_t lid = h ? (v[u] >> 16) : (v[u] & 0xFFFFu);
-                    const uint32_t word = lid / CPW;
-                    const uint32_t sh = (lid - word * CPW) * BITS;
-                    const uint32_t old = lds_add(&bc[word], 1u << sh);
-                    const uint32_t val = ((old >> sh) & MASK) + 1;
-                    if (val >= at_reg) {   // Algorithm 1: the gate check
-                        gate_pass(ht, lg, za, misc, lid, val, k, s);
-                        at_reg = lds_load(&misc[M_AT]);
+        for (int u = 0; u < U; u++) {
+            const uint32_t p0 = cb + u * 64;
+            if (p0 >= total_dw) {
+                off[u] = sent_dw + lane;
+            } else {
+                while (p0 >= c_hi) {   // next run (runs of no dwords are skipped)
+                    si++;
+                    c_lo = c_hi;
+                    c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
+                    dwb = __builtin_amdgcn_readfirstlane(sp_dw[si]);
+                }
+                if (p0 + 64 <= c_hi) {
+                    off[u] = (dwb + (p0 - c_lo)) + lane;   // scalar part + lane
+                } else {   // the piece reaches into later runs or past the end
+                    const uint32_t pos = p0 + lane;
+                    if (pos < total_dw) {
+                        uint32_t li = si, l_lo = c_lo, l_hi = c_hi, l_dwb = dwb;
+                        while (pos >= l_hi) {
+                            li++;
+                            l_lo = l_hi;
+                            l_hi = sp_cum[li + 1];
+                            l_dwb = sp_dw[li];
+                        }
+                        off[u] = l_dwb + (pos - l_lo);
+                    } else {
+                        off[u] = sent_dw + lane;
                     }
                 }
             }
         }
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)   // uniform 64-bit base + 32-bit byte offset
+            v[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + (off[u] << 2));
+        uint32_t at_reg = lds_load(&misc[M_AT]);
+        const uint32_t at_m1 = at_reg - 1;   // val = f + 1 >= AT  <=>  f >= AT - 1
+        // all increments first (no branch between the LDS atomics, so their
+        // latencies overlap), then the gate check
+        uint32_t f[2 * U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const uint32_t lid = h ? (v[u] >> 16) : (v[u] & 0xFFFFu);
+                // field offset (lid mod CPW) * BITS is the low 5 bits of
+                // lid << log2(BITS); shifts and bit-field extracts read only
+                // those bits
+                const uint32_t sh = lid << LBITS;
+                const uint32_t old = lds_add(&bc[lid >> LCPW], 1u << (sh & 31u));
+                f[2 * u + h] = __builtin_amdgcn_ubfe(old, sh, BITS);
+            }
+        }
+        // Algorithm 1's gate check, first for the whole wave at once: the
+        // largest previous count of the lane's postings against AT - 1
+        uint32_t fmax = f[0];
+#pragma unroll
+        for (int j = 1; j < 2 * U; j++)
+            fmax = max(fmax, f[j]);
+        if (__ballot(fmax >= at_m1)) {
+            // Per posting slot j: the passing lanes (not the padding id) add
+            // to ZA[val] at once, and the AT advance runs as soon as a level
+            // fills, so AT stays current for the next gate checks.  The HT
+            // puts go to the wave's queue (a ballot gives the passing lanes
+            // and mbcnt each lane's place) and run in rounds of 64, so the
+            // wave does not serialise on the few lanes that pass.
+#pragma unroll
+            for (int u = 0; u < U; u++)
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const uint32_t lid = h ? (v[u] >> 16) : (v[u] & 0xFFFFu);
+                    const uint32_t val = f[2 * u + h] + 1;
+                    const bool pass = val >= at_reg && lid != kSentinel;
+                    const uint64_t m = __ballot(pass);
+                    if (m) {
+                        passes += (uint32_t)__popcll(m);
+                        const uint32_t zc = pass ? lds_add(&za[val], 1u) + 1 : 0u;
+                        if (__ballot(zc >= k))
+                            advance_at(za, misc, k, s);
+                        at_reg = lds_load(&misc[M_AT]);
+                        const bool keep = pass && val >= at_reg;
+                        const uint64_t mk = __ballot(keep);
+                        if (mk) {
+                            const uint32_t r = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                            if (keep)
+                                gq[qn + r] = (val << 16) | lid;
+                            qn += (uint32_t)__popcll(mk);
+                            if (qn >= 64) {   // one full round of HT puts
+                                const uint32_t e = gq[qn - 64 + lane];
+                                ht_put(ht, lg, misc, e & 0xFFFFu, e >> 16);
+                                qn -= 64;
+                            }
+                        }
+                    }
+                }
+        }
     }
+    // drain the queue
+    for (uint32_t i0q = 0; i0q < qn; i0q += 64)
+        if (i0q + lane < qn) {
+            const uint32_t e = gq[i0q + lane];
+            ht_put(ht, lg, misc, e & 0xFFFFu, e >> 16);
+        }
+    if (lane == 0 && passes)
+        lds_add(&misc[M_PASSES], passes);
     __syncthreads();
     if (tid == 0) {
         // settle: AT advances that raced with ZA increments are finished here
@@ -302,14 +429,13 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
         while (a <= s && za[a] >= k)
             a++;
         misc[M_AT] = a;
-        uint64_t scanned = 0;
-        for (uint32_t i = 0; i < s; i++)
-            scanned += sp_len[i];
+        const uint64_t scanned = misc[M_SCANNED];
         unsigned long long *stats = reinterpret_cast<unsigned long long *>(p.status + 2);
         atomicAdd(&stats[0], (unsigned long long)scanned);
         if (misc[M_OVERFLOW])
             atomicAdd(&stats[1], 1ull);
         atomicAdd(&stats[2], (unsigned long long)misc[M_INSERTS]);
+        atomicAdd(&stats[3], (unsigned long long)misc[M_PASSES]);
     }
     __syncthreads();
 
@@ -355,20 +481,23 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
     const uint32_t n_above = min(misc[M_NABOVE], kk);
     const uint32_t need = kk - n_above;
     // (2) count == AT - 1: the smallest ids, read from the counters in id
-    //     order (a workgroup-wide prefix count over consecutive words).
-    uint32_t done = 0;
-    for (uint32_t wbase = 0; wbase < NW && done < need; wbase += NT) {
-        const uint32_t w = wbase + tid;
-        const uint32_t word = w < NW ? bc[w] : 0u;
+    //     order.  Thread t owns a contiguous range of counter words; a
+    //     workgroup prefix count of the ties turns local order into the rank
+    //     in id order.
+    if (need > 0) {
+        constexpr uint32_t WPT = (NW + NT - 1) / NT;  // words per thread
+        const uint32_t wb = tid * WPT, we = min(NW, wb + WPT);
         uint32_t mine = 0;
+        for (uint32_t w = wb; w < we; w++) {
+            const uint32_t word = bc[w];
 #pragma unroll
-        for (uint32_t f = 0; f < CPW; f++) {
-            const uint32_t lid = w * CPW + f;
-            mine += (w < NW && lid < tile_n && ((word >> (f * BITS)) & MASK) == thr) ? 1u : 0u;
+            for (uint32_t f = 0; f < CPW; f++)
+                mine += (w * CPW + f < tile_n && ((word >> (f * BITS)) & MASK) == thr) ? 1u : 0u;
         }
         uint32_t total = 0;
-        uint32_t r = done + block_exclusive_scan<NT>(mine, misc + M_WAVESUM, &total);
-        if (mine) {
+        uint32_t r = block_exclusive_scan<NT>(mine, misc + M_WAVESUM, &total);
+        for (uint32_t w = wb; w < we && r < need && mine; w++) {
+            const uint32_t word = bc[w];
 #pragma unroll
             for (uint32_t f = 0; f < CPW; f++) {
                 const uint32_t lid = w * CPW + f;
@@ -379,7 +508,6 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
                 }
             }
         }
-        done += total;
     }
     for (uint32_t i = kk + tid; i < k; i += NT)
         out[i] = 0;
@@ -460,16 +588,18 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
 }
 
 __global__ void clear_status_kernel(uint32_t *status) {
-    if (threadIdx.x < 8)
+    if (threadIdx.x < 10)
         status[threadIdx.x] = 0;
 }
 
-template <int BITS, int NT>
+template <int BITS, int NT, int U>
 int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipStream_t st) {
-    auto kern = dump ? scan_cpq_kernel<BITS, NT, true> : scan_cpq_kernel<BITS, NT, false>;
+    auto kern = dump ? scan_cpq_kernel<BITS, NT, U, true> : scan_cpq_kernel<BITS, NT, U, false>;
     GENIE_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds));
+    void *ev = timing_begin(st);
     hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(NT), lds, st, sp);
+    timing_end(ev, st, 0);
     GENIE_HIP(hipGetLastError());
     return GENIE_OK;
 }
@@ -496,6 +626,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.post = ix->post;
     sp.tile_base = ix->tile_base;
     sp.toff = ix->toff;
+    sp.tpad = ix->tpad;
     sp.n = ix->n;
     sp.nkeys1 = ix->nkeys + 1;
     sp.d = ix->d;
@@ -521,14 +652,11 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     }
     hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, stream, sp.status);
     GENIE_HIP(hipGetLastError());
-    constexpr int NT = 512;
+    constexpr int NT = kScanThreads, U = kScanUnroll;
     switch (shape.bits) {
-    case 4: rc = launch_scan<4, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
-    case 5: rc = launch_scan<5, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
-    case 6: rc = launch_scan<6, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
-    case 8: rc = launch_scan<8, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
-    case 10: rc = launch_scan<10, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
-    case 16: rc = launch_scan<16, NT>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 4: rc = launch_scan<4, NT, U>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 8: rc = launch_scan<8, NT, U>(sp, dump, shape.lds_bytes, grid, stream); break;
+    case 16: rc = launch_scan<16, NT, U>(sp, dump, shape.lds_bytes, grid, stream); break;
     default: set_error("no kernel for %d-bit counters", shape.bits); return GENIE_ERANGE;
     }
     if (rc || dump)
@@ -540,7 +668,9 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     mp.k = k;
     mp.out_ids = d_out_ids;
     mp.out_counts = d_out_counts;
+    void *ev = timing_begin(stream);
     hipLaunchKernelGGL(merge_kernel<256>, dim3(n_queries), dim3(256), 0, stream, mp);
+    timing_end(ev, stream, 1);
     GENIE_HIP(hipGetLastError());
     return GENIE_OK;
 }
