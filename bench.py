@@ -4,7 +4,11 @@ A step is one pass of the whole search path over one batch: every query of
 the relational workload (1,000,000 objects x 32 dims, per-dim Zipf(1.1) over
 256 buckets, 1,024 range queries of one item per dim, k = 100) goes through
 the scan + count + c-PQ kernel and the per-query merge, with the index, the
-queries, the outputs and the workspace already resident in HBM.
+queries, the outputs and the workspace already resident in HBM.  Two paths
+are timed, K steps each: the plain c-PQ (AuditThreshold from 1), and the
+learned gate (query features + MLP prediction + gated search with its exact
+fallback), trained beforehand on a separate query set; their answers must be
+identical.  `value` is the faster of the two.
 
 Prints one JSON line.  Besides throughput it reports
   roofline      the scan kernel's algorithmic bytes per launch divided by its
@@ -81,6 +85,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle time for the CPU baseline (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gate", action="store_true", help="skip the learned-gate path")
+    ap.add_argument("--gate-train-queries", type=int, default=4096)
+    ap.add_argument("--gate-epochs", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -102,38 +109,72 @@ def main():
     ws = genie.alloc_workspace(ix, nq, k)
     stream = torch.cuda.current_stream()
 
-    def step():
+    def plain_step():
         genie.genie_search_async(ix, off, items, k, max_items, out_ids, out_cts, ws, stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    # learned gate: trained (outside any timed region) on a separate set of
+    # queries over the same objects, labels = k-th counts of the plain method
+    gate_ids = torch.empty_like(out_ids)
+    gate_cts = torch.empty_like(out_cts)
+    gws = genie.alloc_workspace(ix, nq, k)
+    model = None
+    if not args.no_gate:
+        from paper_1603_08390_amd import gate as gate_mod
+        tq = workloads.queries_random_width(np.random.default_rng(workloads.BASE_SEED + 102),
+                                            inst.values, inst.V, args.gate_train_queries)
+        toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
+        t_ids, t_cts, _ = genie.genie_search_async(ix, toff, titems, k, tq.max_items())
+        tx = genie.genie_gate_features_async(ix, toff, titems, k)
+        ty = t_cts[:, k - 1].float().contiguous()
+        model = gate_mod.GateModel(seed=1)
+        model.train(tx, ty, epochs=args.gate_epochs, batch=256, lr=2e-3, tau=0.1)
+        model.calibrate(model.predict(tx).cpu().numpy(), ty.cpu().numpy(), target=0.01)
+        feats = torch.empty((nq, 64), dtype=torch.float32, device="cuda")
+        pred = torch.empty(nq, dtype=torch.float32, device="cuda")
+
+    def gated_step():
+        genie.genie_gate_features_async(ix, off, items, k, out=feats, stream=stream)
+        model.predict(feats, out=pred, stream=stream)
+        genie.genie_search_gated_async(ix, off, items, k, max_items, pred, model.delta,
+                                       gate_ids, gate_cts, gws, stream)
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        genie.genie_kernel_timing_read(reset=True)   # drop the warmup launches
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # timed regions: exactly K steps of each path; the plain path's kernels
+    # carry HIP event pairs on the launch stream (the roofline's durations)
+    genie.genie_kernel_timing_enable(True)
+    genie.genie_kernel_timing_read(reset=True)
+    elapsed_plain = timed(plain_step)
+    kt = genie.genie_kernel_timing_read(reset=True)
+    genie.genie_kernel_timing_enable(False)
     stats = genie.workspace_stats(ws)
     if stats["status"] != 0:
         raise RuntimeError(f"device status {stats}")
     scanned = stats["postings_scanned"]
+    elapsed_gate = timed(gated_step) if model is not None else None
+    gstats = genie.workspace_stats(gws) if model is not None else None
+    if model is not None:
+        same = bool(torch.equal(gate_ids, out_ids) and torch.equal(gate_cts, out_cts))
+        if not same:
+            raise RuntimeError("gated and plain answers differ")
 
-    # timed region: exactly K steps
-    genie.genie_kernel_timing_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    qps = nq * args.steps / elapsed
-
-    # per-kernel durations: the same K steps again with event pairs around
-    # the library's launches (kept out of the throughput measurement)
-    genie.genie_kernel_timing_enable(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    kt = genie.genie_kernel_timing_read(reset=True)
-    genie.genie_kernel_timing_enable(False)
     scan_ms = kt["scan_ms"] / max(1, kt["scan_launches"])
     merge_ms = kt["merge_ms"] / max(1, kt["merge_launches"])
+
+    qps_plain = nq * args.steps / elapsed_plain
+    use_gate = model is not None and elapsed_gate < elapsed_plain
+    elapsed = elapsed_gate if use_gate else elapsed_plain
+    ms_per_step = elapsed * 1e3 / args.steps
+    qps = nq * args.steps / elapsed
 
     # algorithmic bytes of one scan launch: postings (uint16, read once), the
     # items (12 B), two Position Map offsets per item per tile (8 B), and the
@@ -162,12 +203,25 @@ def main():
                                "over 256 buckets; 1,024 queries, one range item per dim, "
                                "width U{0..8}; k=100",
                    "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V,
-                   "n_queries": nq, "k": k, "path": "plain c-PQ",
+                   "n_queries": nq, "k": k,
+                   "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "atomic_roof": atomic_roof,
-        "ht_inserts_per_step": stats["ht_inserts"],
-        "ht_overflow_tiles": stats["ht_overflow_tiles"],
+        "plain_cpq": {"value": round(qps_plain, 1),
+                      "ms_per_step": round(elapsed_plain * 1e3 / args.steps, 4),
+                      "gate_passes_per_step": stats["gate_passes"],
+                      "ht_inserts_per_step": stats["ht_inserts"],
+                      "ht_overflow_tiles": stats["ht_overflow_tiles"]},
+        "learned_gate": None if model is None else {
+            "value": round(nq * args.steps / elapsed_gate, 1),
+            "ms_per_step": round(elapsed_gate * 1e3 / args.steps, 4),
+            "speedup_vs_plain": round(elapsed_plain / elapsed_gate, 4),
+            "identical_results": True,
+            "gate_passes_per_step": gstats["gate_passes"],
+            "fallback_queries_per_step": gstats["fallback_queries"],
+            "delta": model.delta, "train_queries": args.gate_train_queries,
+            "epochs": args.gate_epochs},
     }
     if not args.no_cpu_baseline and args.cpu_budget > 0:
         result["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget)

@@ -159,6 +159,92 @@ int genie_search_async(const genie_index *ix, const uint64_t *d_q_offsets,
                        void *d_workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Search with a learned initial gate (an extension of Algorithm 1: the paper
+ * starts the AuditThreshold at 1).  For each query the AuditThreshold starts
+ * at max(1, floor(d_gate[q] - gate_delta)), capped at s + 1, where d_gate[q]
+ * is a prediction of the query's k-th match count (genie_gate_forward_async).
+ * Fewer increments then pass the gate.  Results are identical to
+ * genie_search_async: a query whose k-th count lies below its start is
+ * detected after the scan and answered again with AT = 1 on the device (the
+ * number of such queries is left as a uint32 at byte offset 40 of the
+ * workspace).
+ *   d_gate: device, n_queries float32.  gate_delta >= 0.
+ *   Other arguments and the workspace as genie_search_async.
+ */
+int genie_search_gated_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                             const genie_item *d_items, uint64_t n_items, uint32_t n_queries,
+                             uint32_t max_items, uint32_t k, const float *d_gate,
+                             float gate_delta, uint32_t *d_out_ids, uint32_t *d_out_counts,
+                             void *d_workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Queries of the LSH transform (Section 4.1.1): query q is the items
+ * (i, sig[q][i], sig[q][i]) for i = 0..m-1, i.e. one exact keyword per hash
+ * function.
+ *   d_sig: device, n_queries * m uint32 (genie_lsh_signatures output).
+ *   d_items: device, n_queries * m items; d_q_offsets: device, n_queries + 1.
+ */
+int genie_lsh_items_async(const uint32_t *d_sig, uint32_t n_queries, uint32_t m,
+                          genie_item *d_items, uint64_t *d_q_offsets, void *stream);
+
+/* ---- learned initial gate: features and a 64-128-128-1 MLP ------------- */
+
+#define GENIE_GATE_FEATURES 64
+#define GENIE_GATE_PARAMS 24961 /* W1[128][64] b1[128] W2[128][128] b2[128] w3[128] b3 */
+
+/*
+ * The 64 features of each query, from the posting counts L_i of the keywords
+ * each item covers (an index lookup per item, no scan).  With p_i = L_i / n,
+ * mu = sum p_i, sigma^2 = sum p_i (1 - p_i) and z the upper k/n quantile of
+ * the standard normal:
+ *   0 s/512 (s = items)  1 mu/64  2 sigma/8  3 (mu + z sigma)/64  4 max p_i
+ *   5 sum p_i^2/64  6 sum p_i^3/64  7 z/8
+ *   8..23  items with L_i > 0 by the largest b <= 15 with L_i 2^b <= n, /64
+ *   24..55 the 32 largest p_i, descending (0 past s)
+ *   56 items with L_i = 0, /64   57 items with 4 L_i >= n, /64   58..63 zero
+ * Sums are formed in float64 in a fixed order and stored as float32.
+ *   d_features: device, n_queries * 64 float32, row-major.
+ * Errors: GENIE_EINVAL.
+ */
+int genie_gate_features_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                              const genie_item *d_items, uint64_t n_items, uint32_t n_queries,
+                              uint32_t k, float *d_features, void *stream);
+
+/*
+ * Predictions out[i] = w3 . relu(W2 relu(W1 x_i + b1) + b2) + b3, float32
+ * arithmetic, each dot product summed in index order (a row's prediction does
+ * not depend on the other rows).  Weights: exactly one of d_w_bf16 (bfloat16
+ * bit patterns) or d_w_f32, GENIE_GATE_PARAMS values in the layout above.
+ *   d_x: device, n * 64 float32; d_out: device, n float32.
+ */
+int genie_gate_forward_async(const uint16_t *d_w_bf16, const float *d_w_f32, const float *d_x,
+                             uint32_t n, float *d_out, void *stream);
+
+/* Workspace bytes for genie_gate_backward_async over n samples. */
+size_t genie_gate_workspace_size(uint32_t n);
+
+/*
+ * Gradient of the mean pinball (quantile tau) loss over n samples,
+ * L = mean(tau r if r >= 0 else (tau - 1) r), r = y - prediction, with
+ * respect to the parameters (layout above), into d_grad (GENIE_GATE_PARAMS
+ * float32), and the loss into *d_loss (may be NULL).  Per-workgroup partial
+ * sums are added in a fixed order.  0 < tau < 1.
+ */
+int genie_gate_backward_async(const uint16_t *d_w_bf16, const float *d_w_f32, const float *d_x,
+                              const float *d_y, uint32_t n, float tau, float *d_grad,
+                              float *d_loss, void *d_workspace, size_t workspace_bytes,
+                              void *stream);
+
+/*
+ * One Adam step on the float32 master weights (moments d_m, d_v; step counts
+ * from 1), then d_w_bf16 (may be NULL) = master rounded to nearest bfloat16,
+ * ties to even.
+ */
+int genie_gate_adam_async(float *d_master, uint16_t *d_w_bf16, const float *d_grad, float *d_m,
+                          float *d_v, uint32_t step, float lr, float beta1, float beta2, float eps,
+                          void *stream);
+
+/*
  * Full match-count vectors (the scan-and-count step of Section 3.2 with the
  * Bitmap Counter of Section 3.3.1), for checking and analysis.
  *   d_out_counts: device, n_queries * n_objects uint32; row q at q*n_objects.

@@ -37,8 +37,12 @@ EXPORTED = (
     "genie_build_index", "genie_free_index", "genie_index_info_get", "genie_search",
     "genie_search_workspace_size", "genie_search_async", "genie_match_count_async",
     "genie_lsh_signatures", "genie_last_error", "genie_kernel_timing_enable",
-    "genie_kernel_timing_read",
+    "genie_kernel_timing_read", "genie_search_gated_async", "genie_gate_features_async",
+    "genie_gate_forward_async", "genie_gate_workspace_size", "genie_gate_backward_async",
+    "genie_gate_adam_async", "genie_lsh_items_async",
 )
+GATE_FEATURES = 64
+GATE_PARAMS = 24961
 
 
 class GenieError(RuntimeError):
@@ -93,6 +97,22 @@ def load() -> ctypes.CDLL:
     lib.genie_kernel_timing_enable.restype = ctypes.c_int
     lib.genie_kernel_timing_read.argtypes = [ctypes.POINTER(_KernelTimes), ctypes.c_int]
     lib.genie_kernel_timing_read.restype = ctypes.c_int
+    f32 = ctypes.c_float
+    lib.genie_search_gated_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, f32, vp, vp, vp,
+                                             sz, vp]
+    lib.genie_search_gated_async.restype = ctypes.c_int
+    lib.genie_gate_features_async.argtypes = [vp, vp, vp, u64, u32, u32, vp, vp]
+    lib.genie_gate_features_async.restype = ctypes.c_int
+    lib.genie_gate_forward_async.argtypes = [vp, vp, vp, u32, vp, vp]
+    lib.genie_gate_forward_async.restype = ctypes.c_int
+    lib.genie_gate_workspace_size.argtypes = [u32]
+    lib.genie_gate_workspace_size.restype = sz
+    lib.genie_gate_backward_async.argtypes = [vp, vp, vp, vp, u32, f32, vp, vp, vp, sz, vp]
+    lib.genie_gate_backward_async.restype = ctypes.c_int
+    lib.genie_gate_adam_async.argtypes = [vp, vp, vp, vp, vp, u32, f32, f32, f32, f32, vp]
+    lib.genie_gate_adam_async.restype = ctypes.c_int
+    lib.genie_lsh_items_async.argtypes = [vp, u32, u32, vp, vp, vp]
+    lib.genie_lsh_items_async.restype = ctypes.c_int
     lib.genie_last_error.argtypes = []
     lib.genie_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -224,6 +244,96 @@ def genie_search_async(index: Index, d_q_offsets, d_items, k: int, max_items: in
     return out_ids, out_counts, workspace
 
 
+def genie_search_gated_async(index: Index, d_q_offsets, d_items, k: int, max_items: int,
+                             d_gate, gate_delta: float, out_ids=None, out_counts=None,
+                             workspace=None, stream=None):
+    """Search with the AuditThreshold starting at the predicted k-th count
+    (minus gate_delta); identical results to genie_search_async."""
+    import torch
+    nq = d_q_offsets.numel() - 1
+    dev = d_q_offsets.device
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if out_counts is None:
+        out_counts = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = alloc_workspace(index, nq, k, dev)
+    if nq <= 0:
+        return out_ids, out_counts, workspace
+    _check(load().genie_search_gated_async(index.handle, _dev_ptr(d_q_offsets), _dev_ptr(d_items),
+                                           d_items.numel() // 3, nq, int(max_items), int(k),
+                                           _dev_ptr(d_gate), float(gate_delta), _dev_ptr(out_ids),
+                                           _dev_ptr(out_counts), _dev_ptr(workspace),
+                                           workspace.numel(), _stream_handle(stream)))
+    return out_ids, out_counts, workspace
+
+
+def genie_gate_features_async(index: Index, d_q_offsets, d_items, k: int, out=None, stream=None):
+    """Query features [nq, 64] float32 on the device."""
+    import torch
+    nq = d_q_offsets.numel() - 1
+    if out is None:
+        out = torch.empty((max(nq, 0), GATE_FEATURES), dtype=torch.float32,
+                          device=d_q_offsets.device)
+    if nq <= 0:
+        return out
+    _check(load().genie_gate_features_async(index.handle, _dev_ptr(d_q_offsets), _dev_ptr(d_items),
+                                            d_items.numel() // 3, nq, int(k), _dev_ptr(out),
+                                            _stream_handle(stream)))
+    return out
+
+
+def _weights(w):
+    import torch
+    if w.dtype == torch.int16 or w.dtype == torch.uint16:
+        return _dev_ptr(w), None
+    if w.dtype == torch.float32:
+        return None, _dev_ptr(w)
+    raise TypeError("weights must be bf16 bit patterns (int16) or float32")
+
+
+def genie_gate_forward_async(weights, d_x, out=None, stream=None):
+    import torch
+    n = d_x.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=d_x.device)
+    wb, wf = _weights(weights)
+    _check(load().genie_gate_forward_async(wb, wf, _dev_ptr(d_x), n, _dev_ptr(out),
+                                           _stream_handle(stream)))
+    return out
+
+
+def genie_gate_workspace_size(n: int) -> int:
+    return int(load().genie_gate_workspace_size(int(n)))
+
+
+def genie_gate_backward_async(weights, d_x, d_y, tau: float, grad=None, loss=None,
+                              workspace=None, stream=None):
+    import torch
+    n = d_x.shape[0]
+    dev = d_x.device
+    if grad is None:
+        grad = torch.empty(GATE_PARAMS, dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = torch.empty(genie_gate_workspace_size(n), dtype=torch.uint8, device=dev)
+    wb, wf = _weights(weights)
+    _check(load().genie_gate_backward_async(wb, wf, _dev_ptr(d_x), _dev_ptr(d_y), n, float(tau),
+                                            _dev_ptr(grad), _dev_ptr(loss), _dev_ptr(workspace),
+                                            workspace.numel(), _stream_handle(stream)))
+    return grad, loss, workspace
+
+
+def genie_gate_adam_async(master, w_bf16, grad, m, v, step: int, lr: float, beta1: float = 0.9,
+                          beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    _check(load().genie_gate_adam_async(_dev_ptr(master),
+                                        _dev_ptr(w_bf16) if w_bf16 is not None else None,
+                                        _dev_ptr(grad), _dev_ptr(m), _dev_ptr(v), int(step),
+                                        float(lr), float(beta1), float(beta2), float(eps),
+                                        _stream_handle(stream)))
+
+
 def genie_match_count_async(index: Index, d_q_offsets, d_items, max_items: int,
                             out=None, workspace=None, stream=None):
     """Full match-count vectors [nq, n] (uint32 stored in int32 tensors)."""
@@ -270,14 +380,26 @@ def genie_kernel_timing_read(reset: bool = True) -> dict:
             "merge_launches": t.merge_launches, "merge_ms": t.merge_ms}
 
 
+def genie_lsh_items_async(d_sig, stream=None):
+    """Exact-match query items (i, sig[i], sig[i]) for signature rows; returns
+    (q_offsets int64 [nq+1], items int32 [nq*m, 3]) on the device."""
+    import torch
+    nq, m = d_sig.shape
+    off = torch.empty(nq + 1, dtype=torch.int64, device=d_sig.device)
+    items = torch.empty((max(nq * m, 1), 3), dtype=torch.int32, device=d_sig.device)
+    _check(load().genie_lsh_items_async(_dev_ptr(d_sig) if nq else None, nq, m, _dev_ptr(items),
+                                        _dev_ptr(off), _stream_handle(stream)))
+    return off, items
+
+
 def workspace_stats(workspace) -> dict:
     """Status flags and counters left in a workspace by the last search."""
-    head = workspace[:40].cpu().numpy()
+    head = workspace[:48].cpu().numpy()
     status = int(head[:4].view(np.uint32)[0])
     stats = head[8:40].view(np.uint64)
     return {"status": status, "postings_scanned": int(stats[0]),
             "ht_overflow_tiles": int(stats[1]), "ht_inserts": int(stats[2]),
-            "gate_passes": int(stats[3])}
+            "gate_passes": int(stats[3]), "fallback_queries": int(head[40:44].view(np.uint32)[0])}
 
 
 def queries_to_device(q_offsets: np.ndarray, items: np.ndarray, device="cuda"):

@@ -40,7 +40,8 @@ WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint
     L.status = 0;
     L.tile_kth = 256;
     L.cand = align256(L.tile_kth + pairs * sizeof(uint32_t));
-    L.total = align256(L.cand + pairs * (uint64_t)k * sizeof(uint64_t));
+    L.fb_list = align256(L.cand + pairs * (uint64_t)k * sizeof(uint64_t));
+    L.total = align256(L.fb_list + (uint64_t)n_queries * sizeof(uint32_t));
     return L;
 }
 
@@ -165,6 +166,16 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
     tile_base[0] = 0;
     for (uint32_t t = 0; t < T; t++)
         tile_base[t + 1] = tile_base[t] + tile_size[t];
+    // postings per keyword over all tiles, as a prefix (query features)
+    std::vector<uint64_t> kcum(nkeys + 1, 0);
+    for (uint32_t t = 0; t < T; t++) {
+        const uint32_t *row = &toff[(uint64_t)t * (nkeys + 1)];
+        const uint32_t *prow = &tpad[(uint64_t)t * (nkeys + 1)];
+        for (uint64_t key = 0; key < nkeys; key++)
+            kcum[key + 1] += (row[key + 1] - row[key]) - (prow[key + 1] - prow[key]);
+    }
+    for (uint64_t key = 0; key < nkeys; key++)
+        kcum[key + 1] += kcum[key];
     const uint64_t stored = tile_base[T];
     std::vector<uint16_t> post(stored, kSentinel);
     next.store(0);
@@ -212,6 +223,9 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
     if (e == hipSuccess) e = hipMalloc((void **)&ix->tile_base, bb);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->toff, bt);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->tpad, bt);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->kcum, kcum.size() * sizeof(uint64_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(ix->kcum, kcum.data(), kcum.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->post, post.data(), bp, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->tile_base, tile_base.data(), bb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->toff, toff.data(), bt, hipMemcpyHostToDevice);
@@ -221,7 +235,7 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
         genie_free_index(ix);
         return rc;
     }
-    ix->device_bytes = bp + bb + 2 * bt;
+    ix->device_bytes = bp + bb + 2 * bt + kcum.size() * sizeof(uint64_t);
     *out = ix;
     return GENIE_OK;
 }
@@ -237,6 +251,7 @@ extern "C" void genie_free_index(genie_index *ix) {
     if (ix->tile_base) (void)hipFree(ix->tile_base);
     if (ix->toff) (void)hipFree(ix->toff);
     if (ix->tpad) (void)hipFree(ix->tpad);
+    if (ix->kcum) (void)hipFree(ix->kcum);
     if (sw)
         (void)hipSetDevice(cur);
     delete ix;
@@ -308,6 +323,39 @@ extern "C" int genie_search_async(const genie_index *ix, const uint64_t *d_q_off
     return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, k, d_out_ids,
                          d_out_counts, nullptr, d_workspace, workspace_bytes,
                          (hipStream_t)stream);
+}
+
+extern "C" int genie_search_gated_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                                        const genie_item *d_items, uint64_t n_items,
+                                        uint32_t n_queries, uint32_t max_items, uint32_t k,
+                                        const float *d_gate, float gate_delta,
+                                        uint32_t *d_out_ids, uint32_t *d_out_counts,
+                                        void *d_workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = check_common(ix, n_queries, k);
+    if (rc)
+        return rc;
+    if (n_queries == 0)
+        return GENIE_OK;
+    if (!d_q_offsets || !d_items || !d_out_ids || !d_out_counts || !d_workspace || !d_gate) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (max_items > GENIE_MAX_ITEMS) {
+        set_error("max_items=%u above %u", max_items, GENIE_MAX_ITEMS);
+        return GENIE_ERANGE;
+    }
+    if (((uintptr_t)d_workspace & 255) != 0) {
+        set_error("workspace must be 256-byte aligned");
+        return GENIE_EINVAL;
+    }
+    if (!(gate_delta >= 0.0f)) {
+        set_error("gate_delta must be >= 0");
+        return GENIE_EINVAL;
+    }
+    return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, k, d_out_ids,
+                         d_out_counts, nullptr, d_workspace, workspace_bytes,
+                         (hipStream_t)stream, d_gate, gate_delta);
 }
 
 extern "C" int genie_match_count_async(const genie_index *ix, const uint64_t *d_q_offsets,

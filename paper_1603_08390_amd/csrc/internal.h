@@ -48,6 +48,7 @@ struct genie_index {
     uint64_t *tile_base = nullptr; // n_tiles + 1 element offsets of each tile in post
     uint32_t *toff = nullptr;      // n_tiles rows of nkeys + 1 padded offsets, relative to tile_base
     uint32_t *tpad = nullptr;      // n_tiles rows of nkeys + 1 counts of padded runs before a keyword
+    uint64_t *kcum = nullptr;      // nkeys + 1 prefix counts of postings per keyword (all tiles)
     uint64_t stored_postings = 0;  // elements in post (real + padding + trailing sentinels)
     uint64_t device_bytes = 0;
     int device = 0;
@@ -68,11 +69,14 @@ int hip_fail(hipError_t e, const char *what);
 
 // Workspace layout of one search call (all offsets 256-byte aligned).
 struct WorkspaceLayout {
-    size_t status = 0;     // uint32 flags + pad, then uint64 stats[3]
+    size_t status = 0;     // uint32 flags + pad, uint64 stats[4], uint32 fallback count
     size_t tile_kth = 0;   // uint32 [n_queries * n_tiles]
     size_t cand = 0;       // uint64 [n_queries * n_tiles * k]
+    size_t fb_list = 0;    // uint32 [n_queries] (gated search)
     size_t total = 0;
 };
+// uint32 word of the status block that counts fallback queries
+constexpr uint32_t kStatusFallbackWord = 10;
 WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint32_t k);
 
 // Counter width and table sizes picked for one search call.
@@ -86,7 +90,8 @@ int search_shape(uint32_t max_items, uint32_t k, SearchShape *out);
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
-                  size_t workspace_bytes, hipStream_t stream);
+                  size_t workspace_bytes, hipStream_t stream, const float *d_gate = nullptr,
+                  float gate_delta = 0.0f);
 
 // Opt-in kernel timing (timing.cpp): begin returns an event handle or null.
 void *timing_begin(hipStream_t st);

@@ -11,6 +11,7 @@
 // points and of the projection vectors staged in LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -91,10 +92,44 @@ __global__ __launch_bounds__(256) void lsh_kernel(LshParams p) {
     }
 }
 
+__global__ void lsh_items_kernel(const uint32_t *sig, uint32_t nq, uint32_t m, uint32_t *items,
+                                 uint64_t *q_off) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t total = (uint64_t)nq * m;
+    if (i < total) {
+        const uint32_t f = (uint32_t)(i % m);
+        const uint32_t v = sig[i];
+        items[3 * i] = f;
+        items[3 * i + 1] = v;
+        items[3 * i + 2] = v;
+    }
+    if (i <= nq)
+        q_off[i] = i * m;
+}
+
 }  // namespace
 }  // namespace genie
 
 using namespace genie;
+
+extern "C" int genie_lsh_items_async(const uint32_t *d_sig, uint32_t n_queries, uint32_t m,
+                                     genie_item *d_items, uint64_t *d_q_offsets, void *stream) {
+    clear_error();
+    if (!d_items || !d_q_offsets || (n_queries && !d_sig) || m == 0) {
+        set_error("bad arguments");
+        return GENIE_EINVAL;
+    }
+    const uint64_t total = std::max<uint64_t>((uint64_t)n_queries * m, (uint64_t)n_queries + 1);
+    const uint64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7FFFFFFFull) {
+        set_error("too many items");
+        return GENIE_EINVAL;
+    }
+    hipLaunchKernelGGL(lsh_items_kernel, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream,
+                       d_sig, n_queries, m, reinterpret_cast<uint32_t *>(d_items), d_q_offsets);
+    GENIE_HIP(hipGetLastError());
+    return GENIE_OK;
+}
 
 extern "C" int genie_lsh_signatures(const float *d_points, uint64_t n, uint32_t dim,
                                     const float *d_a, const float *d_b, float w, uint32_t m,

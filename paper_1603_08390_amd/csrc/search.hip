@@ -38,13 +38,22 @@ struct ScanParams {
     uint32_t *tile_kth;     // [nq][n_tiles]
     uint32_t *full_counts;  // [nq][n] (count dump mode) or null
     uint32_t *status;       // flags word; stats as uint64 at status + 2
+    const float *gate;      // predicted k-th count per query (gated search) or null
+    float gate_delta;       // safety margin subtracted from the prediction
+    const uint32_t *qlist;  // query of each row (fallback pass) or null
+    const uint32_t *qcount; // rows in qlist (device) or null
 };
 
 struct MergeParams {
     const uint64_t *cand;
     const uint32_t *tile_kth;
+    uint64_t n;
     uint32_t n_tiles, k;
     uint32_t *out_ids, *out_counts;
+    uint32_t *fb_count;      // gated search: queries to answer again (device counter)
+    uint32_t *fb_list;       // ... and their indices
+    const uint32_t *qlist;   // fallback pass: query of each block
+    const uint32_t *qcount;
 };
 
 // Answer order key: larger is better; count in the high word, then smaller
@@ -215,7 +224,10 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
     if (pair >= npairs)
         return;
     const uint32_t t = (uint32_t)(pair / p.nq);
-    const uint32_t q = (uint32_t)(pair % p.nq);
+    const uint32_t qrow = (uint32_t)(pair % p.nq);
+    if (p.qcount && qrow >= *p.qcount)
+        return;
+    const uint32_t q = p.qlist ? p.qlist[qrow] : qrow;
     const uint32_t tid = threadIdx.x;
 
     const uint64_t tile0 = (uint64_t)t * kTile;
@@ -232,8 +244,15 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
         ht[i] = 0;
     for (uint32_t i = tid; i < p.max_items + 2; i += NT)
         za[i] = 0;
+    // AuditThreshold starts at 1 (Algorithm 1), or, in the gated search, at
+    // the predicted k-th count minus a margin (never above s + 1)
+    uint32_t at0 = 1;
+    if (p.gate) {
+        const float g = fminf(p.gate[q] - p.gate_delta, (float)(s + 1));
+        at0 = g >= 2.0f ? (uint32_t)floorf(g) : 1u;   // NaN and low values give 1
+    }
     if (tid < 32)
-        misc[tid] = (tid == M_AT) ? 1u : 0u;
+        misc[tid] = (tid == M_AT) ? at0 : 0u;
     __syncthreads();
     // Position Map lookup (Section 3.2), restricted to this tile: the keywords
     // of one dim are adjacent, so item (dim, lo, hi) is the single run
@@ -484,6 +503,7 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
     //     order.  Thread t owns a contiguous range of counter words; a
     //     workgroup prefix count of the ties turns local order into the rank
     //     in id order.
+    uint32_t emitted = n_above;
     if (need > 0) {
         constexpr uint32_t WPT = (NW + NT - 1) / NT;  // words per thread
         const uint32_t wb = tid * WPT, we = min(NW, wb + WPT);
@@ -496,6 +516,7 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
         }
         uint32_t total = 0;
         uint32_t r = block_exclusive_scan<NT>(mine, misc + M_WAVESUM, &total);
+        emitted += min(need, total);   // fewer only when AT started above the tile's k-th count
         for (uint32_t w = wb; w < we && r < need && mine; w++) {
             const uint32_t word = bc[w];
 #pragma unroll
@@ -509,7 +530,7 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
             }
         }
     }
-    for (uint32_t i = kk + tid; i < k; i += NT)
+    for (uint32_t i = emitted + tid; i < k; i += NT)
         out[i] = 0;
     if (tid == 0)
         p.tile_kth[row] = thr;
@@ -523,7 +544,10 @@ template <int NT>
 __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
     __shared__ uint64_t buf[kMergeBuf];
     __shared__ uint32_t s_cnt, s_floor;
-    const uint32_t q = blockIdx.x, tid = threadIdx.x, k = p.k;
+    if (p.qcount && blockIdx.x >= *p.qcount)
+        return;
+    const uint32_t q = p.qlist ? p.qlist[blockIdx.x] : blockIdx.x;
+    const uint32_t tid = threadIdx.x, k = p.k;
     const uint64_t ncand = (uint64_t)p.n_tiles * k;
     const uint64_t *cand = p.cand + (uint64_t)q * ncand;
     if (tid == 0) {
@@ -537,7 +561,8 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
     atomicMax(&s_floor, fl);
     __syncthreads();
     const uint32_t floor_count = s_floor;
-    uint32_t kc = 0;  // valid keys at the front of buf, sorted descending
+    uint32_t kc = 0;     // valid keys at the front of buf, sorted descending
+    uint32_t kept = 0;   // candidates that reached the floor
     for (uint64_t c0 = 0; c0 < ncand; c0 += kMergeChunk) {
         const uint64_t c1 = min<uint64_t>(ncand, c0 + kMergeChunk);
         for (uint64_t i = c0 + tid; i < c1; i += NT) {
@@ -555,6 +580,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
         __syncthreads();
         if (added == 0)
             continue;
+        kept += added;
         const uint32_t m = kc + added;
         uint32_t np2 = 1;
         while (np2 < m)
@@ -580,6 +606,14 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
         }
         kc = min(m, k);
     }
+    // Gated search: when fewer than min(k, n) candidates reached the floor,
+    // the query's k-th count lies below where its AT started; it is answered
+    // again with AT = 1.
+    if (p.fb_count && kept < min<uint64_t>(k, p.n)) {
+        if (tid == 0)
+            p.fb_list[atomicAdd(p.fb_count, 1u)] = q;
+        return;
+    }
     for (uint32_t i = tid; i < k; i += NT) {
         const uint64_t key = i < kc ? buf[i] : 0ull;
         p.out_ids[(uint64_t)q * k + i] = 0xFFFFFFFFu - (uint32_t)key;
@@ -588,7 +622,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
 }
 
 __global__ void clear_status_kernel(uint32_t *status) {
-    if (threadIdx.x < 10)
+    if (threadIdx.x < 16)
         status[threadIdx.x] = 0;
 }
 
@@ -609,7 +643,8 @@ int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipS
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
-                  size_t workspace_bytes, hipStream_t stream) {
+                  size_t workspace_bytes, hipStream_t stream, const float *d_gate,
+                  float gate_delta) {
     const bool dump = d_full_counts != nullptr;
     const WorkspaceLayout L = workspace_layout(ix, n_queries, k);
     if (workspace_bytes < L.total) {
@@ -645,6 +680,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.tile_kth = reinterpret_cast<uint32_t *>(ws + L.tile_kth);
     sp.full_counts = d_full_counts;
     sp.status = reinterpret_cast<uint32_t *>(ws + L.status);
+    sp.gate = d_gate;
+    sp.gate_delta = gate_delta;
     const uint64_t grid = sp.per_xcd * 8;
     if (grid > 0x7FFFFFFFull) {
         set_error("too many (query, tile) pairs in one call");
@@ -664,13 +701,42 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     MergeParams mp{};
     mp.cand = sp.cand;
     mp.tile_kth = sp.tile_kth;
+    mp.n = ix->n;
     mp.n_tiles = ix->n_tiles;
     mp.k = k;
     mp.out_ids = d_out_ids;
     mp.out_counts = d_out_counts;
+    uint32_t *fb_count = sp.status + kStatusFallbackWord;
+    uint32_t *fb_list = reinterpret_cast<uint32_t *>(ws + L.fb_list);
+    if (d_gate) {
+        mp.fb_count = fb_count;
+        mp.fb_list = fb_list;
+    }
     void *ev = timing_begin(stream);
     hipLaunchKernelGGL(merge_kernel<256>, dim3(n_queries), dim3(256), 0, stream, mp);
     timing_end(ev, stream, 1);
+    GENIE_HIP(hipGetLastError());
+    if (!d_gate)
+        return GENIE_OK;
+    // fallback pass: the flagged queries again with AT = 1 (workgroups past
+    // the device-side count exit at once)
+    ScanParams fp = sp;
+    fp.gate = nullptr;
+    fp.qlist = fb_list;
+    fp.qcount = fb_count;
+    switch (shape.bits) {
+    case 4: rc = launch_scan<4, NT, U>(fp, false, shape.lds_bytes, grid, stream); break;
+    case 8: rc = launch_scan<8, NT, U>(fp, false, shape.lds_bytes, grid, stream); break;
+    default: rc = launch_scan<16, NT, U>(fp, false, shape.lds_bytes, grid, stream); break;
+    }
+    if (rc)
+        return rc;
+    MergeParams fm = mp;
+    fm.fb_count = nullptr;
+    fm.fb_list = nullptr;
+    fm.qlist = fb_list;
+    fm.qcount = fb_count;
+    hipLaunchKernelGGL(merge_kernel<256>, dim3(n_queries), dim3(256), 0, stream, fm);
     GENIE_HIP(hipGetLastError());
     return GENIE_OK;
 }

@@ -1,0 +1,83 @@
+"""The serving loop's scheduling on the CPU with a fake executor: grouping
+by (index, k) in arrival order, the batch limit, admission against the
+memory budget (back-pressure, never failure), and every request answered
+once."""
+import numpy as np
+
+from paper_1603_08390_amd import serving
+
+
+class FakeExecutor:
+    def __init__(self, bytes_per_query=100, polls=3):
+        self.bytes_per_query = bytes_per_query
+        self.polls = polls
+        self.launched = []
+        self.live = 0
+        self.max_live = 0
+
+    def free_memory(self):
+        return 10 ** 9
+
+    def need_bytes(self, group):
+        return self.bytes_per_query * len(group)
+
+    def launch(self, slot, group):
+        self.launched.append((slot, [q.rid for q in group], group[0].target, group[0].k))
+        self.live += 1
+        self.max_live = max(self.max_live, self.live)
+        return {"left": self.polls, "group": group}
+
+    def done(self, h):
+        h["left"] -= 1
+        if h["left"] <= 0:
+            self.live -= 1
+            return True
+        return False
+
+    def fetch(self, h):
+        g = h["group"]
+        ids = np.array([[q.rid] * q.k for q in g], dtype=np.uint32)
+        return ids, ids.copy()
+
+
+def _reqs(n, rng):
+    out = []
+    for i in range(n):
+        out.append(serving.Request(i, "a" if i % 3 else "b", int(rng.choice([1, 2])), 0.0,
+                                   items=np.zeros((1, 3), np.uint32)))
+    return out
+
+
+def test_every_request_answered_once_and_grouped():
+    ex = FakeExecutor()
+    srv = serving.Server(slots=3, max_batch=5, hbm_budget=10 ** 6, executor=ex)
+    reqs = _reqs(40, np.random.default_rng(0))
+    res = srv.run(reqs)
+    assert sorted(r.rid for r in res) == list(range(40))
+    for r in res:
+        assert r.ids[0] == r.rid
+    by_id = {q.rid: q for q in reqs}
+    for slot, rids, target, k in ex.launched:
+        assert len(rids) <= 5
+        assert all(by_id[r].target == target and by_id[r].k == k for r in rids)
+    assert ex.max_live <= 3
+    assert srv.in_use == 0
+
+
+def test_memory_budget_queues_instead_of_failing():
+    ex = FakeExecutor(bytes_per_query=100)
+    srv = serving.Server(slots=4, max_batch=8, hbm_budget=250, executor=ex)
+    res = srv.run(_reqs(30, np.random.default_rng(1)))
+    assert len(res) == 30
+    assert srv.waited_for_memory > 0
+    for _, rids, _, _ in ex.launched:
+        assert len(rids) * 100 <= 250
+
+
+def test_arrival_order_is_respected():
+    ex = FakeExecutor(polls=1)
+    srv = serving.Server(slots=1, max_batch=1, hbm_budget=10 ** 6, executor=ex)
+    reqs = [serving.Request(i, "a", 1, 0.001 * (9 - i), items=np.zeros((1, 3), np.uint32))
+            for i in range(10)]
+    srv.run(reqs)
+    assert [rids[0] for _, rids, _, _ in ex.launched] == list(range(9, -1, -1))
