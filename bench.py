@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--no-gate", action="store_true", help="skip the learned-gate path")
     ap.add_argument("--gate-train-queries", type=int, default=4096)
     ap.add_argument("--gate-epochs", type=int, default=30)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 3 times (calibrates the HBM "
+                         "byte counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -99,6 +102,15 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return
     inst = workloads.relational()
     nq, k = inst.queries.n_queries, inst.k
     ix = genie.Index(inst.values, inst.V)

@@ -104,6 +104,15 @@ int genie_build_index(const uint32_t *values, uint64_t n_objects, uint32_t n_dim
 /* Free an index and its device memory.  NULL is ignored. */
 void genie_free_index(genie_index *ix);
 
+/*
+ * Launch shape of the scan kernel for searches on this index: threads per
+ * workgroup (512 or 1024) and posting dwords each thread loads per step (4
+ * or 8).  Results do not depend on it; speed does (an autotuner picks it).
+ * Not to be changed while a search on the index is being enqueued.
+ * Errors: GENIE_EINVAL.
+ */
+int genie_index_set_scan_shape(genie_index *ix, uint32_t threads, uint32_t unroll);
+
 /* Describe an index.  Errors: GENIE_EINVAL. */
 int genie_index_info_get(const genie_index *ix, genie_index_info *out);
 

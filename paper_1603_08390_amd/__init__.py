@@ -39,7 +39,7 @@ EXPORTED = (
     "genie_lsh_signatures", "genie_last_error", "genie_kernel_timing_enable",
     "genie_kernel_timing_read", "genie_search_gated_async", "genie_gate_features_async",
     "genie_gate_forward_async", "genie_gate_workspace_size", "genie_gate_backward_async",
-    "genie_gate_adam_async", "genie_lsh_items_async",
+    "genie_gate_adam_async", "genie_lsh_items_async", "genie_index_set_scan_shape",
 )
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
@@ -113,6 +113,8 @@ def load() -> ctypes.CDLL:
     lib.genie_gate_adam_async.restype = ctypes.c_int
     lib.genie_lsh_items_async.argtypes = [vp, u32, u32, vp, vp, vp]
     lib.genie_lsh_items_async.restype = ctypes.c_int
+    lib.genie_index_set_scan_shape.argtypes = [vp, u32, u32]
+    lib.genie_index_set_scan_shape.restype = ctypes.c_int
     lib.genie_last_error.argtypes = []
     lib.genie_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -192,6 +194,13 @@ class Index:
 
 def genie_build_index(values: np.ndarray, n_buckets: int) -> Index:
     return Index(values, n_buckets)
+
+
+def genie_index_set_scan_shape(index: Index, threads: int, unroll: int):
+    _check(load().genie_index_set_scan_shape(index.handle, int(threads), int(unroll)))
+
+
+SCAN_SHAPES = ((512, 4), (512, 8), (1024, 4), (1024, 8))
 
 
 def genie_search(index: Index, q_offsets: np.ndarray, items: np.ndarray, k: int

@@ -45,7 +45,7 @@ WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint
     return L;
 }
 
-int search_shape(uint32_t max_items, uint32_t k, SearchShape *out) {
+int search_shape(uint32_t max_items, uint32_t k, int threads, SearchShape *out) {
     // Counter width b: counts reach at most max_items; one more code (all
     // ones) marks an object already emitted during selection.
     static const int widths[] = {4, 8, 16};
@@ -69,7 +69,7 @@ int search_shape(uint32_t max_items, uint32_t k, SearchShape *out) {
     const size_t bc_words = 65536 / cpw;
     // dynamic part: misc, HT, ZA, run table, gate queues
     size_t words = 32 + (1u << lg) + (max_items + 2) + 2ull * max_items + 1 +
-                   (size_t)(kScanThreads / 64) * kGateQueue;
+                   (size_t)(threads / 64) * kGateQueue;
     out->bits = bits;
     out->ht_log2 = lg;
     out->lds_bytes = words * 4;
@@ -255,6 +255,18 @@ extern "C" void genie_free_index(genie_index *ix) {
     if (sw)
         (void)hipSetDevice(cur);
     delete ix;
+}
+
+extern "C" int genie_index_set_scan_shape(genie_index *ix, uint32_t threads, uint32_t unroll) {
+    clear_error();
+    if (!ix || !((threads == 512 || threads == 1024) && (unroll == 4 || unroll == 8))) {
+        set_error("scan shape %u x %u not available (threads 512|1024, unroll 4|8)", threads,
+                  unroll);
+        return GENIE_EINVAL;
+    }
+    ix->scan_threads = (int)threads;
+    ix->scan_unroll = (int)unroll;
+    return GENIE_OK;
 }
 
 extern "C" int genie_index_info_get(const genie_index *ix, genie_index_info *out) {
@@ -446,7 +458,7 @@ extern "C" int genie_search(const genie_index *ix, const uint64_t *q_offsets,
             return GENIE_EINVAL;
         }
     SearchShape shape;
-    rc = search_shape(max_items, k, &shape);
+    rc = search_shape(max_items, k, ix->scan_threads, &shape);
     if (rc)
         return rc;
 

@@ -19,22 +19,16 @@ constexpr uint64_t kSentinelDwords = 64;   // all-sentinel dwords after each til
 // LDS available to one workgroup on gfx950.
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
-// Scan kernel launch shape: threads per workgroup (at least 512: the run
-// table prefix sum gives each thread two of at most 1024 runs) and posting
-// dwords each thread loads per step.
-#ifndef GENIE_SCAN_THREADS
-#define GENIE_SCAN_THREADS 512
-#endif
-#ifndef GENIE_SCAN_UNROLL
-#define GENIE_SCAN_UNROLL 8
-#endif
-constexpr int kScanThreads = GENIE_SCAN_THREADS;
+// Scan kernel launch shapes compiled in: threads per workgroup in {512,
+// 1024} (at least 512: the run table prefix sum gives each thread two of at
+// most 1024 runs) and posting dwords each thread loads per step in {4, 8}.
+// The default is the fastest measured on the relational workload; an index
+// can be given another one (genie_index_set_scan_shape).
+constexpr int kScanThreadsDefault = 512;
+constexpr int kScanUnrollDefault = 4;
 // Gate queue entries per wave (LDS words): fewer than 64 wait between
 // rounds, and one posting slot adds at most 64.
 constexpr uint32_t kGateQueue = 128;
-constexpr int kScanUnroll = GENIE_SCAN_UNROLL;
-static_assert(kScanThreads >= 512 && kScanThreads <= 1024 && kScanThreads % 64 == 0,
-              "scan workgroup size");
 
 struct genie_index {
     uint64_t n = 0;          // objects
@@ -52,6 +46,8 @@ struct genie_index {
     uint64_t stored_postings = 0;  // elements in post (real + padding + trailing sentinels)
     uint64_t device_bytes = 0;
     int device = 0;
+    int scan_threads = kScanThreadsDefault;   // launch shape of the scan kernel
+    int scan_unroll = kScanUnrollDefault;
 };
 
 namespace genie {
@@ -85,7 +81,7 @@ struct SearchShape {
     uint32_t ht_log2 = 0;  // hash-table slots = 1 << ht_log2
     size_t lds_bytes = 0;  // dynamic LDS of the scan kernel (the counters are static)
 };
-int search_shape(uint32_t max_items, uint32_t k, SearchShape *out);
+int search_shape(uint32_t max_items, uint32_t k, int threads, SearchShape *out);
 
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,

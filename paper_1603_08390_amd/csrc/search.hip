@@ -638,6 +638,27 @@ int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipS
     return GENIE_OK;
 }
 
+template <int BITS>
+int dispatch_shape(int nt, int u, const ScanParams &sp, bool dump, size_t lds, uint64_t grid,
+                   hipStream_t st) {
+    if (nt == 512 && u == 4) return launch_scan<BITS, 512, 4>(sp, dump, lds, grid, st);
+    if (nt == 512 && u == 8) return launch_scan<BITS, 512, 8>(sp, dump, lds, grid, st);
+    if (nt == 1024 && u == 4) return launch_scan<BITS, 1024, 4>(sp, dump, lds, grid, st);
+    if (nt == 1024 && u == 8) return launch_scan<BITS, 1024, 8>(sp, dump, lds, grid, st);
+    set_error("no scan kernel for %d threads x %d dwords", nt, u);
+    return GENIE_EINVAL;
+}
+
+int dispatch_scan(int bits, int nt, int u, const ScanParams &sp, bool dump, size_t lds,
+                  uint64_t grid, hipStream_t st) {
+    switch (bits) {
+    case 4: return dispatch_shape<4>(nt, u, sp, dump, lds, grid, st);
+    case 8: return dispatch_shape<8>(nt, u, sp, dump, lds, grid, st);
+    case 16: return dispatch_shape<16>(nt, u, sp, dump, lds, grid, st);
+    default: set_error("no kernel for %d-bit counters", bits); return GENIE_ERANGE;
+    }
+}
+
 }  // namespace
 
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
@@ -653,7 +674,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
         return GENIE_EINVAL;
     }
     SearchShape shape;
-    int rc = search_shape(max_items, k, &shape);
+    int rc = search_shape(max_items, k, ix->scan_threads, &shape);
     if (rc)
         return rc;
     char *ws = static_cast<char *>(d_workspace);
@@ -689,13 +710,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     }
     hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, stream, sp.status);
     GENIE_HIP(hipGetLastError());
-    constexpr int NT = kScanThreads, U = kScanUnroll;
-    switch (shape.bits) {
-    case 4: rc = launch_scan<4, NT, U>(sp, dump, shape.lds_bytes, grid, stream); break;
-    case 8: rc = launch_scan<8, NT, U>(sp, dump, shape.lds_bytes, grid, stream); break;
-    case 16: rc = launch_scan<16, NT, U>(sp, dump, shape.lds_bytes, grid, stream); break;
-    default: set_error("no kernel for %d-bit counters", shape.bits); return GENIE_ERANGE;
-    }
+    rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, sp, dump, shape.lds_bytes,
+                       grid, stream);
     if (rc || dump)
         return rc;
     MergeParams mp{};
@@ -724,11 +740,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     fp.gate = nullptr;
     fp.qlist = fb_list;
     fp.qcount = fb_count;
-    switch (shape.bits) {
-    case 4: rc = launch_scan<4, NT, U>(fp, false, shape.lds_bytes, grid, stream); break;
-    case 8: rc = launch_scan<8, NT, U>(fp, false, shape.lds_bytes, grid, stream); break;
-    default: rc = launch_scan<16, NT, U>(fp, false, shape.lds_bytes, grid, stream); break;
-    }
+    rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, fp, false, shape.lds_bytes,
+                       grid, stream);
     if (rc)
         return rc;
     MergeParams fm = mp;
