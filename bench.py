@@ -1,21 +1,37 @@
 """Benchmark: match-count top-k search with c-PQ on one MI355X.
 
-A step is one pass of the whole search path over one batch: every query of
-the relational workload (1,000,000 objects x 32 dims, per-dim Zipf(1.1) over
-256 buckets, 1,024 range queries of one item per dim, k = 100) goes through
-the scan + count + c-PQ kernel and the per-query merge, with the index, the
-queries, the outputs and the workspace already resident in HBM.  Two paths
-are timed, K steps each: the plain c-PQ (AuditThreshold from 1), and the
-learned gate (query features + MLP prediction + gated search with its exact
-fallback), trained beforehand on a separate query set; their answers must be
-identical.  `value` is the faster of the two.
+A step is one pass of the whole search path over one batch of queries, with
+the index, the queries, the outputs and the workspace already resident in
+HBM.  Two paths are timed, K steps each, on the same batch: the plain c-PQ
+(AuditThreshold from 1), and the learned gate (query features + MLP
+prediction + gated search with its exact fallback), trained beforehand on a
+separate query set over the same objects; their answers must be identical.
+`value` is the faster of the two.
+
+Workloads (--workload):
+  relational  (default) 1,000,000 objects x 32 dims, per-dim Zipf(1.1) over
+              256 buckets, 1,024 range queries of one item per dim, k = 100.
+  ann         tau-ANN: 1,000,000 float32 points in 128-d, 237 E2LSH functions
+              re-hashed into 8,192 buckets, 4,096 perturbed query points,
+              k = 100.  A step hashes the query points (LSH kernel), forms
+              their exact-match items and searches; recall@100 and the
+              approximation ratio against exact l2 are reported.
+  uneven      10,000,000 objects x 64 dims, Zipf(1.1) over 1,024 buckets,
+              16,384 queries of 4..512 items in one launch, k = 100; the scan
+              shape is picked by the autotuner first.
+  serving     requests mixing the relational and the ANN shapes at k in
+              {10, 100, 1000} through the continuous-batching loop: the
+              saturated rate (all requests at once), then Poisson arrivals at
+              0.7x the saturated plain rate, with the learned gate off and on;
+              p50/p99 latency and queries/s.
 
 Prints one JSON line.  Besides throughput it reports
   roofline      the scan kernel's algorithmic bytes per launch divided by its
                 mean HIP-event duration on the launch stream, against the
                 8 TB/s HBM peak; `traffic` holds the HBM bytes per launch
                 measured by rocprofv3 counters when a committed counter summary
-                for this exact kernel source is present (else null);
+                for this exact kernel source and workload is present (else
+                null);
   atomic_roof   counter increments per second against the measured rate of
                 conflict-free LDS atomics;
   cpu_baseline  the CPU oracle (plain C inverted-index scan, one thread) on a
@@ -35,12 +51,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "queries/sec at k=100, 1M objects, oracle-exact; learned-gate vs plain c-PQ"
+METRICS = {
+    "relational": METRIC,
+    "ann": "queries/sec at k=100, tau-ANN 1M points x 128-d, LSH hashing included; "
+           "learned-gate vs plain c-PQ",
+    "uneven": "queries/sec at k=100, 10M objects, 16,384 uneven queries in one launch; "
+              "learned-gate vs plain c-PQ",
+    "serving": "queries/sec and p50/p99 latency of the request loop, relational + tau-ANN mix, "
+               "k in {10,100,1000}; learned gate off and on",
+}
 HBM_PEAK_GBS = 8000.0
 # Conflict-free LDS atomic add (with return), lane-consecutive addresses,
 # measured on MI355X: 8.34e12/s over the chip (13.6 per CU per 2.4 GHz clock).
 LDS_ATOMIC_PEAK = 8.34e12
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "scan_cpq_relational_pmc.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1603_08390_amd", "csrc", "search.hip")
+
+
+def pmc_summary_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"scan_cpq_{workload}_pmc.json")
 
 
 def kernel_source_hash() -> str:
@@ -48,11 +76,11 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per scan launch from the committed rocprofv3 counter summary,
     only if it was taken on the current kernel source."""
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(pmc_summary_path(workload)) as f:
             pmc = json.load(f)
     except (OSError, ValueError):
         return None
@@ -61,14 +89,14 @@ def measured_traffic():
     return pmc.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(inst, budget_s: float):
+def cpu_baseline(values, V, queries, k, budget_s: float, chunk: int = 64):
     import oracle
-    idx = oracle.build_csr(inst.values, inst.V)
-    nq = inst.queries.n_queries
+    idx = oracle.build_csr(values, V)
+    nq = queries.n_queries
     done, t0 = 0, time.perf_counter()
     while done < nq and time.perf_counter() - t0 < budget_s:
-        q1 = min(nq, done + 64)
-        oracle.search_idx(idx, inst.queries, inst.k, done, q1)
+        q1 = min(nq, done + chunk)
+        oracle.search_idx(idx, queries, k, done, q1)
         done = q1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
@@ -77,17 +105,419 @@ def cpu_baseline(inst, budget_s: float):
             "cpu": platform.processor() or platform.machine()}
 
 
+def train_gate(genie, torch, ix, sets, epochs: int):
+    """Gate model trained on (features, k-th count of the plain method) pairs
+    of the given (d_q_offsets, d_items, max_items, k) query sets."""
+    from paper_1603_08390_amd import gate as gate_mod
+    xs, ys = [], []
+    for (toff, titems, tmax, k) in sets:
+        _, t_cts, _ = genie.genie_search_async(ix, toff, titems, k, tmax)
+        xs.append(genie.genie_gate_features_async(ix, toff, titems, k))
+        ys.append(t_cts[:, k - 1].float())
+    tx = torch.cat(xs).contiguous()
+    ty = torch.cat(ys).contiguous()
+    model = gate_mod.GateModel(seed=1)
+    model.train(tx, ty, epochs=epochs, batch=256, lr=2e-3, tau=0.1)
+    model.calibrate(model.predict(tx).cpu().numpy(), ty.cpu().numpy(), target=0.01)
+    return model
+
+
+class SearchBench:
+    """Times the plain and the gated path over one resident batch.
+
+    `prep(stream)` returns the device (q_offsets, items) of the batch for
+    this step: constant tensors for item queries, or the output of the LSH
+    kernels for point queries (their time is then part of the step)."""
+
+    def __init__(self, genie, torch, ix, nq, k, max_items, prep):
+        self.genie, self.torch, self.ix = genie, torch, ix
+        self.nq, self.k, self.max_items, self.prep = nq, k, max_items, prep
+        self.stream = torch.cuda.current_stream()
+        self.ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+        self.cts = torch.empty_like(self.ids)
+        self.ws = genie.alloc_workspace(ix, nq, k)
+        self.gids = torch.empty_like(self.ids)
+        self.gcts = torch.empty_like(self.ids)
+        self.gws = genie.alloc_workspace(ix, nq, k)
+        self.feats = torch.empty((nq, 64), dtype=torch.float32, device="cuda")
+        self.pred = torch.empty(nq, dtype=torch.float32, device="cuda")
+        self.model = None
+
+    def plain_step(self):
+        off, items = self.prep(self.stream)
+        self.genie.genie_search_async(self.ix, off, items, self.k, self.max_items, self.ids,
+                                      self.cts, self.ws, self.stream)
+
+    def gated_step(self):
+        g, m = self.genie, self.model
+        off, items = self.prep(self.stream)
+        g.genie_gate_features_async(self.ix, off, items, self.k, out=self.feats,
+                                    stream=self.stream)
+        m.predict(self.feats, out=self.pred, stream=self.stream)
+        g.genie_search_gated_async(self.ix, off, items, self.k, self.max_items, self.pred,
+                                   m.delta, self.gids, self.gcts, self.gws, self.stream)
+
+    def timed(self, step, steps, warmup):
+        """Warmup steps, then exactly `steps` steps between two device
+        synchronisations; kernel event timings of the warmup are dropped."""
+        torch, g = self.torch, self.genie
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        g.genie_kernel_timing_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def run(self, steps, warmup, s_total):
+        g = self.genie
+        g.genie_kernel_timing_enable(True)
+        g.genie_kernel_timing_read(reset=True)
+        el_plain = self.timed(self.plain_step, steps, warmup)
+        kt = g.genie_kernel_timing_read(reset=True)
+        stats = g.workspace_stats(self.ws)
+        if stats["status"] != 0:
+            raise RuntimeError(f"device status {stats}")
+        el_gate, gstats, gkt = None, None, None
+        if self.model is not None:
+            el_gate = self.timed(self.gated_step, steps, warmup)
+            gkt = g.genie_kernel_timing_read(reset=True)
+            gstats = g.workspace_stats(self.gws)
+            if gstats["status"] != 0:
+                raise RuntimeError(f"device status {gstats}")
+            if not (self.torch.equal(self.gids, self.ids) and
+                    self.torch.equal(self.gcts, self.cts)):
+                raise RuntimeError("gated and plain answers differ")
+        g.genie_kernel_timing_enable(False)
+
+        nq, k = self.nq, self.k
+        scan_ms = kt["scan_ms"] / max(1, kt["scan_launches"])
+        merge_ms = kt["merge_ms"] / max(1, kt["merge_launches"])
+        use_gate = el_gate is not None and el_gate < el_plain
+        elapsed = el_gate if use_gate else el_plain
+        scanned = stats["postings_scanned"]
+        # algorithmic bytes of one scan launch: postings (uint16, read once),
+        # the items (12 B), two Position Map offsets per item per tile (8 B),
+        # and the answer (8 B per result)
+        T = self.ix.info.n_tiles
+        alg_bytes = 2 * scanned + 12 * s_total + 8 * s_total * T + 8 * k * nq
+        achieved = alg_bytes / (scan_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "kernel": "scan_cpq_kernel",
+                    "kernel_ms": round(scan_ms, 4), "merge_kernel_ms": round(merge_ms, 4),
+                    "alg_bytes_per_launch": alg_bytes}
+        rate = scanned / (scan_ms * 1e-3)
+        atomic_roof = {"achieved": rate, "peak": LDS_ATOMIC_PEAK, "unit": "increments/s",
+                       "frac": round(rate / LDS_ATOMIC_PEAK, 4), "postings_per_step": scanned}
+        plain = {"value": round(nq * steps / el_plain, 1),
+                 "ms_per_step": round(el_plain * 1e3 / steps, 4),
+                 "gate_passes_per_step": stats["gate_passes"],
+                 "ht_inserts_per_step": stats["ht_inserts"],
+                 "ht_overflow_tiles": stats["ht_overflow_tiles"]}
+        learned = None
+        if el_gate is not None:
+            learned = {"value": round(nq * steps / el_gate, 1),
+                       "ms_per_step": round(el_gate * 1e3 / steps, 4),
+                       "speedup_vs_plain": round(el_plain / el_gate, 4),
+                       "identical_results": True,
+                       "gate_passes_per_step": gstats["gate_passes"],
+                       "fallback_queries_per_step": gstats["fallback_queries"],
+                       "scan_ms_per_step": round(gkt["scan_ms"] / steps, 4),
+                       "delta": self.model.delta}
+        return {"value": round(nq * steps / elapsed, 1),
+                "ms_per_step": round(elapsed * 1e3 / steps, 4),
+                "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
+                "roofline": roofline, "atomic_roof": atomic_roof,
+                "plain_cpq": plain, "learned_gate": learned}
+
+
+def line(args, workload, res, config, dtype="u32"):
+    out = {"metric": METRICS[workload], "value": res["value"], "unit": "queries/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": dict(config, path=res["path"], parallelism="single GPU")}
+    for key in ("roofline", "atomic_roof", "plain_cpq", "learned_gate"):
+        out[key] = res[key]
+    out["roofline"]["traffic"] = measured_traffic(workload)
+    return out
+
+
+def bench_relational(args, torch, genie, workloads):
+    inst = workloads.relational()
+    nq, k = inst.queries.n_queries, inst.k
+    ix = genie.Index(inst.values, inst.V)
+    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
+    sb = SearchBench(genie, torch, ix, nq, k, inst.queries.max_items(), lambda st: (off, items))
+    if not args.no_gate:
+        tq = workloads.queries_random_width(np.random.default_rng(workloads.BASE_SEED + 102),
+                                            inst.values, inst.V, args.gate_train_queries)
+        toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
+        sb.model = train_gate(genie, torch, ix, [(toff, titems, tq.max_items(), k)],
+                              args.gate_epochs)
+    res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]))
+    out = line(args, "relational", res, {
+        "workload": "relational: 1,000,000 objects x 32 dims, per-dim Zipf(1.1) over 256 "
+                    "buckets; 1,024 queries, one range item per dim, width U{0..8}; k=100",
+        "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V, "n_queries": nq, "k": k})
+    if out["learned_gate"]:
+        out["learned_gate"].update(train_queries=args.gate_train_queries,
+                                   epochs=args.gate_epochs)
+    out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget)
+                           if not args.no_cpu_baseline and args.cpu_budget > 0 else None)
+    ix.free()
+    return out
+
+
+def lsh_device(torch, inp):
+    return {"a": torch.from_numpy(inp.a).cuda(), "b": torch.from_numpy(inp.b).cuda(),
+            "rehash": torch.from_numpy(inp.rehash.view(np.int64)).cuda(), "w": inp.w,
+            "log2_buckets": inp.log2_buckets}
+
+
+def ann_index(torch, genie, inp, lsh):
+    """Index over the GPU LSH signatures of the points (built outside any
+    timed region)."""
+    sig = genie.genie_lsh_signatures(torch.from_numpy(inp.points).cuda(), lsh["a"], lsh["b"],
+                                     lsh["w"], lsh["rehash"], lsh["log2_buckets"])
+    torch.cuda.synchronize()
+    sig_h = genie.as_uint32(sig)
+    del sig
+    return genie.Index(sig_h, 1 << inp.log2_buckets), sig_h
+
+
+def exact_knn_gpu(torch, P, Q, k, chunk=256):
+    """Exact l2 k nearest neighbours in float32 on the device (evaluation
+    only: recall is a property of LSH, not of the search path)."""
+    pn = (P * P).sum(1)
+    ids, dist = [], []
+    for i in range(0, Q.shape[0], chunk):
+        q = Q[i:i + chunk]
+        d2 = pn[None, :] - 2.0 * (q @ P.t()) + (q * q).sum(1)[:, None]
+        v, j = torch.topk(d2, k, dim=1, largest=False)
+        ids.append(j)
+        dist.append(v.clamp_min(0).sqrt())
+    return torch.cat(ids), torch.cat(dist)
+
+
+def ann_quality(torch, P, Q, found, k):
+    """recall@k and the approximation ratio (mean over queries of the mean
+    ratio of the i-th found distance to the i-th true distance, both sorted;
+    pairs with a zero true distance skipped)."""
+    t_ids, t_dist = exact_knn_gpu(torch, P, Q, k)
+    f = found.long()
+    hit = (f[:, :, None] == t_ids[:, None, :]).any(2).float().mean().item()
+    fd = ((P[f] - Q[:, None, :]) ** 2).sum(2).clamp_min(0).sqrt()
+    fd, _ = torch.sort(fd, dim=1)
+    ok = t_dist > 0
+    r = torch.where(ok, fd / torch.where(ok, t_dist, torch.ones_like(t_dist)),
+                    torch.zeros_like(fd))
+    per_q = r.sum(1) / ok.sum(1).clamp_min(1)
+    return hit, per_q[ok.any(1)].mean().item()
+
+
+def bench_ann(args, torch, genie, workloads):
+    inp = workloads.ann()
+    lsh = lsh_device(torch, inp)
+    ix, sig_h = ann_index(torch, genie, inp, lsh)
+    nq, m, k = inp.queries.shape[0], inp.a.shape[0], inp.k
+    qpts = torch.from_numpy(inp.queries).cuda()
+    qsig = torch.empty((nq, m), dtype=torch.int32, device="cuda")
+    qoff = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    qitems = torch.empty((nq * m, 3), dtype=torch.int32, device="cuda")
+
+    def prep(st):
+        genie.genie_lsh_signatures(qpts, lsh["a"], lsh["b"], lsh["w"], lsh["rehash"],
+                                   lsh["log2_buckets"], out=qsig, stream=st)
+        genie.genie_lsh_items_async(qsig, out=(qoff, qitems), stream=st)
+        return qoff, qitems
+
+    sb = SearchBench(genie, torch, ix, nq, k, m, prep)
+    if not args.no_gate:
+        tq = workloads.ann_queries(np.random.default_rng(workloads.BASE_SEED + 103),
+                                   inp.points, args.gate_train_queries)
+        tsig = genie.genie_lsh_signatures(torch.from_numpy(tq).cuda(), lsh["a"], lsh["b"],
+                                          lsh["w"], lsh["rehash"], lsh["log2_buckets"])
+        toff, titems = genie.genie_lsh_items_async(tsig)
+        sb.model = train_gate(genie, torch, ix, [(toff, titems, m, k)], args.gate_epochs)
+    res = sb.run(args.steps, args.warmup, nq * m)
+    P = torch.from_numpy(inp.points).cuda()
+    rec, ratio = ann_quality(torch, P, qpts, sb.ids, k)
+    out = line(args, "ann", res, {
+        "workload": "tau-ANN: 1,000,000 float32 points x 128 (64-component Gaussian mixture, "
+                    "clipped at 0); 237 E2LSH functions, w=4.0, re-hashed into 8,192 buckets; "
+                    "4,096 perturbed query points; k=100",
+        "n_objects": inp.points.shape[0], "n_functions": m, "n_buckets": 1 << inp.log2_buckets,
+        "n_queries": nq, "k": k})
+    out["quality"] = {"recall_at_100": round(rec, 4), "approximation_ratio": round(ratio, 4),
+                      "queries": nq, "truth": "exact l2, float32 on the device"}
+    if out["learned_gate"]:
+        out["learned_gate"].update(train_queries=args.gate_train_queries,
+                                   epochs=args.gate_epochs)
+    if not args.no_cpu_baseline and args.cpu_budget > 0:
+        qs = workloads.queries_exact(genie.as_uint32(qsig))
+        cb = cpu_baseline(sig_h, 1 << inp.log2_buckets, qs, k, args.cpu_budget)
+        cb["sample"] += "; query signatures from the timed run, hashing not included"
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
+    ix.free()
+    return out
+
+
+def bench_uneven(args, torch, genie, workloads):
+    from paper_1603_08390_amd.autotune import autotune
+    inst = workloads.uneven()
+    nq, k = inst.queries.n_queries, inst.k
+    ix = genie.Index(inst.values, inst.V)
+    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
+    max_items = inst.queries.max_items()
+    # scan shape chosen on a sample of the batch (its first 1,024 queries)
+    sq = inst.queries.subset(range(min(nq, 1024)))
+    soff, sitems = genie.queries_to_device(sq.q_offsets, sq.items)
+    tune = autotune(ix, soff, sitems, k, sq.max_items(), reps=2)
+    sb = SearchBench(genie, torch, ix, nq, k, max_items, lambda st: (off, items))
+    if not args.no_gate:
+        rng = np.random.default_rng(workloads.BASE_SEED + 104)
+        tq = workloads.queries_uneven(rng, inst.values, inst.V, args.gate_train_queries)
+        toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
+        sb.model = train_gate(genie, torch, ix, [(toff, titems, tq.max_items(), k)],
+                              args.gate_epochs)
+    res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]))
+    out = line(args, "uneven", res, {
+        "workload": "uneven: 10,000,000 objects x 64 dims, per-dim Zipf(1.1) over 1,024 "
+                    "buckets; 16,384 queries of U{4..512} range items in one launch; k=100",
+        "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V, "n_queries": nq, "k": k,
+        "scan_shape": f"{tune['threads']}x{tune['unroll']}"})
+    out["autotune_ms"] = tune["ms"]
+    if out["learned_gate"]:
+        out["learned_gate"].update(train_queries=args.gate_train_queries,
+                                   epochs=args.gate_epochs)
+    out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget,
+                                        chunk=1)
+                           if not args.no_cpu_baseline and args.cpu_budget > 0 else None)
+    ix.free()
+    return out
+
+
+def bench_serving(args, torch, genie, workloads):
+    from paper_1603_08390_amd import serving
+    rel = workloads.relational()
+    inp = workloads.ann()
+    lsh = lsh_device(torch, inp)
+    ann_ix, _ = ann_index(torch, genie, inp, lsh)
+    rel_ix = genie.Index(rel.values, rel.V)
+    m = inp.a.shape[0]
+    ks = (10, 100, 1000)
+    gates = {"rel": None, "ann": None}
+    if not args.no_gate:
+        n_t = max(1, args.gate_train_queries // len(ks))
+        tq = workloads.queries_random_width(np.random.default_rng(workloads.BASE_SEED + 105),
+                                            rel.values, rel.V, n_t)
+        toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
+        gates["rel"] = train_gate(genie, torch, rel_ix,
+                                  [(toff, titems, tq.max_items(), kk) for kk in ks],
+                                  args.gate_epochs)
+        tp = workloads.ann_queries(np.random.default_rng(workloads.BASE_SEED + 106),
+                                   inp.points, n_t)
+        tsig = genie.genie_lsh_signatures(torch.from_numpy(tp).cuda(), lsh["a"], lsh["b"],
+                                          lsh["w"], lsh["rehash"], lsh["log2_buckets"])
+        toff, titems = genie.genie_lsh_items_async(tsig)
+        gates["ann"] = train_gate(genie, torch, ann_ix, [(toff, titems, m, kk) for kk in ks],
+                                  args.gate_epochs)
+    res = {"rel": serving.Resident(rel_ix, rel.queries.max_items(), gate=gates["rel"]),
+           "ann": serving.Resident(ann_ix, m, lsh=lsh, gate=gates["ann"])}
+
+    rng = np.random.default_rng(workloads.BASE_SEED + 107)
+    n_req = args.requests
+    kind = rng.integers(0, 2, size=n_req)
+    kk = rng.choice(ks, size=n_req)
+    qrow = rng.integers(0, 1 << 30, size=n_req)
+
+    def requests(arrivals):
+        out = []
+        for i in range(n_req):
+            if kind[i] == 0:
+                q = int(qrow[i] % rel.queries.n_queries)
+                out.append(serving.Request(i, "rel", int(kk[i]), float(arrivals[i]),
+                                           items=rel.queries.items_of(q)))
+            else:
+                q = int(qrow[i] % inp.queries.shape[0])
+                out.append(serving.Request(i, "ann", int(kk[i]), float(arrivals[i]),
+                                           point=inp.queries[q]))
+        return out
+
+    def run(arrivals, use_gate):
+        srv = serving.Server(res, slots=args.slots, max_batch=args.max_batch, use_gate=use_gate)
+        t0 = time.perf_counter()
+        done = srv.run(requests(arrivals))
+        wall = time.perf_counter() - t0
+        s = serving.latency_summary(done, wall)
+        s.update(groups=srv.groups, waited_for_memory=srv.waited_for_memory)
+        return {r.rid: r for r in done}, {key: (round(v, 3) if isinstance(v, float) else v)
+                                          for key, v in s.items()}
+
+    zero = np.zeros(n_req)
+    run(zero, False)                     # warm-up passes, not reported
+    if not args.no_gate:
+        run(zero, True)
+    torch.cuda.synchronize()
+    sat_plain_res, sat_plain = run(zero, False)
+    sat_gate = None
+    if not args.no_gate:
+        sat_gate_res, sat_gate = run(zero, True)
+        for rid, r in sat_plain_res.items():
+            g = sat_gate_res[rid]
+            if not (np.array_equal(r.ids, g.ids) and np.array_equal(r.counts, g.counts)):
+                raise RuntimeError(f"request {rid}: gated and plain answers differ")
+    rate = 0.7 * sat_plain["qps"]
+    arrivals = serving.poisson_arrivals(np.random.default_rng(workloads.BASE_SEED + 108),
+                                        n_req, rate)
+    _, pois_plain = run(arrivals, False)
+    pois_gate = None
+    if not args.no_gate:
+        _, pois_gate = run(arrivals, True)
+    best = pois_gate if pois_gate and pois_gate["qps"] > pois_plain["qps"] else pois_plain
+    ms = n_req / best["qps"] * 1e3 if best["qps"] > 0 else 0.0   # the whole request stream
+    out = {"metric": METRICS["serving"], "value": best["qps"], "unit": "queries/s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic",
+           "config": {"workload": "serving: relational (1M x 32, Zipf(1.1) over 256 buckets) "
+                                  "and tau-ANN (1M x 128, 237 LSH functions) requests, 50/50, "
+                                  "k uniform in {10,100,1000}; Poisson arrivals at 0.7x the "
+                                  "saturated plain rate",
+                      "requests": n_req, "slots": args.slots, "max_batch": args.max_batch,
+                      "offered_qps": round(rate, 1), "parallelism": "single GPU"},
+           "saturated": {"plain": sat_plain, "learned_gate": sat_gate,
+                         "identical_results": sat_gate is not None},
+           "poisson": {"plain": pois_plain, "learned_gate": pois_gate},
+           "cpu_baseline": None}
+    rel_ix.free()
+    ann_ix.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 50; 3 for the uneven workload)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default 5; 1 for the uneven workload)")
+    ap.add_argument("--workload", choices=sorted(METRICS), default="relational")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle time for the CPU baseline (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true", help="skip the learned-gate path")
     ap.add_argument("--gate-train-queries", type=int, default=4096)
     ap.add_argument("--gate-epochs", type=int, default=30)
+    ap.add_argument("--requests", type=int, default=8192, help="serving: number of requests")
+    ap.add_argument("--slots", type=int, default=4, help="serving: execution slots")
+    ap.add_argument("--max-batch", type=int, default=256, help="serving: requests per group")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 3 times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -96,6 +526,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    heavy = args.workload == "uneven"
+    if args.steps is None:
+        args.steps = 3 if heavy else 50
+    if args.warmup is None:
+        args.warmup = 1 if heavy else 5
 
     import torch
     import paper_1603_08390_amd as genie
@@ -111,136 +546,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
         return
-    inst = workloads.relational()
-    nq, k = inst.queries.n_queries, inst.k
-    ix = genie.Index(inst.values, inst.V)
-    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
-    max_items = inst.queries.max_items()
-    out_ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
-    out_cts = torch.empty((nq, k), dtype=torch.int32, device="cuda")
-    ws = genie.alloc_workspace(ix, nq, k)
-    stream = torch.cuda.current_stream()
-
-    def plain_step():
-        genie.genie_search_async(ix, off, items, k, max_items, out_ids, out_cts, ws, stream)
-
-    # learned gate: trained (outside any timed region) on a separate set of
-    # queries over the same objects, labels = k-th counts of the plain method
-    gate_ids = torch.empty_like(out_ids)
-    gate_cts = torch.empty_like(out_cts)
-    gws = genie.alloc_workspace(ix, nq, k)
-    model = None
-    if not args.no_gate:
-        from paper_1603_08390_amd import gate as gate_mod
-        tq = workloads.queries_random_width(np.random.default_rng(workloads.BASE_SEED + 102),
-                                            inst.values, inst.V, args.gate_train_queries)
-        toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
-        t_ids, t_cts, _ = genie.genie_search_async(ix, toff, titems, k, tq.max_items())
-        tx = genie.genie_gate_features_async(ix, toff, titems, k)
-        ty = t_cts[:, k - 1].float().contiguous()
-        model = gate_mod.GateModel(seed=1)
-        model.train(tx, ty, epochs=args.gate_epochs, batch=256, lr=2e-3, tau=0.1)
-        model.calibrate(model.predict(tx).cpu().numpy(), ty.cpu().numpy(), target=0.01)
-        feats = torch.empty((nq, 64), dtype=torch.float32, device="cuda")
-        pred = torch.empty(nq, dtype=torch.float32, device="cuda")
-
-    def gated_step():
-        genie.genie_gate_features_async(ix, off, items, k, out=feats, stream=stream)
-        model.predict(feats, out=pred, stream=stream)
-        genie.genie_search_gated_async(ix, off, items, k, max_items, pred, model.delta,
-                                       gate_ids, gate_cts, gws, stream)
-
-    def timed(step):
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        genie.genie_kernel_timing_read(reset=True)   # drop the warmup launches
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
-
-    # timed regions: exactly K steps of each path; the plain path's kernels
-    # carry HIP event pairs on the launch stream (the roofline's durations)
-    genie.genie_kernel_timing_enable(True)
-    genie.genie_kernel_timing_read(reset=True)
-    elapsed_plain = timed(plain_step)
-    kt = genie.genie_kernel_timing_read(reset=True)
-    genie.genie_kernel_timing_enable(False)
-    stats = genie.workspace_stats(ws)
-    if stats["status"] != 0:
-        raise RuntimeError(f"device status {stats}")
-    scanned = stats["postings_scanned"]
-    elapsed_gate = timed(gated_step) if model is not None else None
-    gstats = genie.workspace_stats(gws) if model is not None else None
-    if model is not None:
-        same = bool(torch.equal(gate_ids, out_ids) and torch.equal(gate_cts, out_cts))
-        if not same:
-            raise RuntimeError("gated and plain answers differ")
-
-    scan_ms = kt["scan_ms"] / max(1, kt["scan_launches"])
-    merge_ms = kt["merge_ms"] / max(1, kt["merge_launches"])
-
-    qps_plain = nq * args.steps / elapsed_plain
-    use_gate = model is not None and elapsed_gate < elapsed_plain
-    elapsed = elapsed_gate if use_gate else elapsed_plain
-    ms_per_step = elapsed * 1e3 / args.steps
-    qps = nq * args.steps / elapsed
-
-    # algorithmic bytes of one scan launch: postings (uint16, read once), the
-    # items (12 B), two Position Map offsets per item per tile (8 B), and the
-    # answer (8 B per result)
-    s_total = int(inst.queries.q_offsets[-1])
-    T = ix.info.n_tiles
-    alg_bytes = 2 * scanned + 12 * s_total + 8 * s_total * T + 8 * k * nq
-    achieved_gbs = alg_bytes / (scan_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
-    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "scan_cpq_kernel",
-                "kernel_ms": round(scan_ms, 4), "merge_kernel_ms": round(merge_ms, 4),
-                "alg_bytes_per_launch": alg_bytes}
-    atomic_rate = scanned / (scan_ms * 1e-3)
-    atomic_roof = {"achieved": atomic_rate, "peak": LDS_ATOMIC_PEAK, "unit": "increments/s",
-                   "frac": round(atomic_rate / LDS_ATOMIC_PEAK, 4),
-                   "postings_per_step": scanned}
-
-    result = {
-        "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": "relational: 1,000,000 objects x 32 dims, per-dim Zipf(1.1) "
-                               "over 256 buckets; 1,024 queries, one range item per dim, "
-                               "width U{0..8}; k=100",
-                   "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V,
-                   "n_queries": nq, "k": k,
-                   "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
-                   "parallelism": "single GPU"},
-        "roofline": roofline,
-        "atomic_roof": atomic_roof,
-        "plain_cpq": {"value": round(qps_plain, 1),
-                      "ms_per_step": round(elapsed_plain * 1e3 / args.steps, 4),
-                      "gate_passes_per_step": stats["gate_passes"],
-                      "ht_inserts_per_step": stats["ht_inserts"],
-                      "ht_overflow_tiles": stats["ht_overflow_tiles"]},
-        "learned_gate": None if model is None else {
-            "value": round(nq * args.steps / elapsed_gate, 1),
-            "ms_per_step": round(elapsed_gate * 1e3 / args.steps, 4),
-            "speedup_vs_plain": round(elapsed_plain / elapsed_gate, 4),
-            "identical_results": True,
-            "gate_passes_per_step": gstats["gate_passes"],
-            "fallback_queries_per_step": gstats["fallback_queries"],
-            "delta": model.delta, "train_queries": args.gate_train_queries,
-            "epochs": args.gate_epochs},
-    }
-    if not args.no_cpu_baseline and args.cpu_budget > 0:
-        result["cpu_baseline"] = cpu_baseline(inst, args.cpu_budget)
-    else:
-        result["cpu_baseline"] = None
-    ix.free()
-    print(json.dumps(result), flush=True)
+    fn = {"relational": bench_relational, "ann": bench_ann, "uneven": bench_uneven,
+          "serving": bench_serving}[args.workload]
+    print(json.dumps(fn(args, torch, genie, workloads)), flush=True)
 
 
 if __name__ == "__main__":

@@ -107,7 +107,8 @@ void genie_free_index(genie_index *ix);
 /*
  * Launch shape of the scan kernel for searches on this index: threads per
  * workgroup (512 or 1024) and posting dwords each thread loads per step (4
- * or 8).  Results do not depend on it; speed does (an autotuner picks it).
+ * or 8); a new index starts at 1024 x 4.  Results do not depend on it;
+ * speed does (an autotuner picks it).
  * Not to be changed while a search on the index is being enqueued.
  * Errors: GENIE_EINVAL.
  */

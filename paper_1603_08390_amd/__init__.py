@@ -389,13 +389,19 @@ def genie_kernel_timing_read(reset: bool = True) -> dict:
             "merge_launches": t.merge_launches, "merge_ms": t.merge_ms}
 
 
-def genie_lsh_items_async(d_sig, stream=None):
+def genie_lsh_items_async(d_sig, out=None, stream=None):
     """Exact-match query items (i, sig[i], sig[i]) for signature rows; returns
-    (q_offsets int64 [nq+1], items int32 [nq*m, 3]) on the device."""
+    (q_offsets int64 [nq+1], items int32 [nq*m, 3]) on the device, written
+    into `out` = (q_offsets, items) when given."""
     import torch
     nq, m = d_sig.shape
-    off = torch.empty(nq + 1, dtype=torch.int64, device=d_sig.device)
-    items = torch.empty((max(nq * m, 1), 3), dtype=torch.int32, device=d_sig.device)
+    if out is None:
+        off = torch.empty(nq + 1, dtype=torch.int64, device=d_sig.device)
+        items = torch.empty((max(nq * m, 1), 3), dtype=torch.int32, device=d_sig.device)
+    else:
+        off, items = out
+        if off.numel() != nq + 1 or items.shape[0] < nq * m or items.shape[1] != 3:
+            raise ValueError("output buffers do not fit the signatures")
     _check(load().genie_lsh_items_async(_dev_ptr(d_sig) if nq else None, nq, m, _dev_ptr(items),
                                         _dev_ptr(off), _stream_handle(stream)))
     return off, items

@@ -24,7 +24,7 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // most 1024 runs) and posting dwords each thread loads per step in {4, 8}.
 // The default is the fastest measured on the relational workload; an index
 // can be given another one (genie_index_set_scan_shape).
-constexpr int kScanThreadsDefault = 512;
+constexpr int kScanThreadsDefault = 1024;
 constexpr int kScanUnrollDefault = 4;
 // Gate queue entries per wave (LDS words): fewer than 64 wait between
 // rounds, and one posting slot adds at most 64.

@@ -189,8 +189,19 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32
     return before + incl - v;
 }
 
+// Occupancy: with 8- or 4-bit counters the workgroup's LDS (64 or 32 KB of
+// counters plus the gate, queues and table) lets two 1024-thread workgroups
+// share a CU, i.e. 8 waves per SIMD, if the kernel fits 64 VGPRs; the scan
+// is bound by the latency of its loads and LDS atomics, so that occupancy is
+// asked for explicitly.  16-bit counters (128 KB) allow one workgroup per CU.
+template <int BITS, int NT>
+constexpr int scan_waves_per_eu() {
+    return (NT == 1024 && BITS != 16) ? 8 : 1;
+}
+
 template <int BITS, int NT, int U, bool DUMP>
-__global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<BITS, NT>())))
+void scan_cpq_kernel(ScanParams p) {
     static_assert(BITS == 4 || BITS == 8 || BITS == 16, "power-of-two counter width");
     constexpr uint32_t CPW = 32 / BITS;                   // counters per word
     constexpr uint32_t LCPW = BITS == 4 ? 3 : (BITS == 8 ? 2 : 1);   // log2(CPW)
@@ -379,12 +390,23 @@ __global__ __launch_bounds__(NT) void scan_cpq_kernel(ScanParams p) {
         for (int u = 0; u < U; u++) {
 #pragma unroll
             for (int h = 0; h < 2; h++) {
-                const uint32_t lid = h ? (v[u] >> 16) : (v[u] & 0xFFFFu);
-                // field offset (lid mod CPW) * BITS is the low 5 bits of
-                // lid << log2(BITS); shifts and bit-field extracts read only
-                // those bits
-                const uint32_t sh = lid << LBITS;
-                const uint32_t old = lds_add(&bc[lid >> LCPW], 1u << (sh & 31u));
+                // The counter of id x sits in word x >> log2(CPW), field
+                // (x mod CPW) * BITS, which is the low 5 bits of x << log2(BITS)
+                // (shifts and bit-field extracts read only those bits), so
+                // the field offset and the word's byte address come straight
+                // from the posting dword, without isolating the id first.
+                const uint32_t w = v[u];
+                uint32_t sh, a;
+                if (h == 0) {
+                    sh = w << LBITS;
+                    a = BITS == 8 ? (w & 0xFFFCu) : BITS == 4 ? ((w >> 1) & 0x7FFCu) : ((w << 1) & 0x1FFFCu);
+                } else {
+                    sh = (w >> 16) << LBITS;
+                    a = BITS == 8 ? ((w >> 16) & 0xFFFCu) : BITS == 4 ? ((w >> 17) & 0x7FFCu) : ((w >> 15) & 0x1FFFCu);
+                }
+                uint32_t inc;   // 1 << (sh mod 32): the shift unit masks the amount
+                asm("v_lshlrev_b32 %0, %1, 1" : "=v"(inc) : "v"(sh));
+                const uint32_t old = lds_add(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(bc) + a), inc);
                 f[2 * u + h] = __builtin_amdgcn_ubfe(old, sh, BITS);
             }
         }

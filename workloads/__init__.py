@@ -237,9 +237,7 @@ def ann(n: int = 1_000_000, dim: int = 128, nq: int = 4096, m: int = 237,
         x = means[comp] + np.float32(sigma) * ro.standard_normal((r1 - r0, dim), dtype=np.float32)
         np.maximum(x, 0.0, out=x)
         points[r0:r1] = x
-    src = rq.integers(0, n, size=nq)
-    queries = points[src] + np.float32(qsigma) * rq.standard_normal((nq, dim), dtype=np.float32)
-    np.maximum(queries, 0.0, out=queries)
+    queries = ann_queries(rq, points, nq, qsigma)
     a = rl.standard_normal((m, dim), dtype=np.float32)
     b = rl.uniform(0.0, w, size=m).astype(np.float32)
     b = np.minimum(b, np.nextafter(np.float32(w), np.float32(0)))
@@ -249,8 +247,16 @@ def ann(n: int = 1_000_000, dim: int = 128, nq: int = 4096, m: int = 237,
     rehash = np.empty(2 * m, dtype=np.uint64)
     rehash[0::2] = A
     rehash[1::2] = B
-    return AnnInputs(points, queries.astype(np.float32), a, b, float(w), rehash,
-                     int(log2_buckets), k)
+    return AnnInputs(points, queries, a, b, float(w), rehash, int(log2_buckets), k)
+
+
+def ann_queries(rng, points: np.ndarray, nq: int, qsigma: float = 0.1) -> np.ndarray:
+    """Queries = random data points + N(0, qsigma^2) per coordinate, clipped at 0."""
+    n, dim = points.shape
+    src = rng.integers(0, n, size=nq)
+    q = points[src] + np.float32(qsigma) * rng.standard_normal((nq, dim), dtype=np.float32)
+    np.maximum(q, 0.0, out=q)
+    return q.astype(np.float32)
 
 
 def random_small(rng, n: int, d: int, V: int, nq: int, max_items: int,
