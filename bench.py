@@ -9,6 +9,8 @@ separate query set over the same objects; their answers must be identical.
 `value` is the faster of the two.
 
 Workloads (--workload):
+  tiny        10,000 objects x 16 dims, values uniform in [0, 64), 100
+              queries of one [v-2, v+2] item per dim, k = 10 (launch-bound).
   relational  (default) 1,000,000 objects x 32 dims, per-dim Zipf(1.1) over
               256 buckets, 1,024 range queries of one item per dim, k = 100.
   ann         tau-ANN: 1,000,000 float32 points in 128-d, 237 E2LSH functions
@@ -22,8 +24,9 @@ Workloads (--workload):
   serving     requests mixing the relational and the ANN shapes at k in
               {10, 100, 1000} through the continuous-batching loop: the
               saturated rate (all requests at once), then Poisson arrivals at
-              0.7x the saturated plain rate, with the learned gate off and on;
-              p50/p99 latency and queries/s.
+              0.3, 0.5, 0.7 and 0.9x the saturated plain rate (0.7 is the
+              headline), with the learned gate off and on; p50/p99 latency and
+              queries/s, and each (index, k) group's device time alone.
 
 Prints one JSON line.  Besides throughput it reports
   roofline      the scan kernel's algorithmic bytes per launch divided by its
@@ -34,7 +37,8 @@ Prints one JSON line.  Besides throughput it reports
                 null);
   atomic_roof   counter increments per second against the measured rate of
                 conflict-free LDS atomics;
-  cpu_baseline  the CPU oracle (plain C inverted-index scan, one thread) on a
+  cpu_baseline  the CPU oracle (plain C inverted-index scan) on the host's
+                cores (up to 16 threads; the one-thread rate beside it) over a
                 bounded sample of the same batch.
 """
 import argparse
@@ -53,6 +57,7 @@ sys.path.insert(0, ROOT)
 METRIC = "queries/sec at k=100, 1M objects, oracle-exact; learned-gate vs plain c-PQ"
 METRICS = {
     "relational": METRIC,
+    "tiny": "queries/sec at k=10, 10K objects x 16 dims (launch-bound); learned-gate vs plain c-PQ",
     "ann": "queries/sec at k=100, tau-ANN 1M points x 128-d, LSH hashing included; "
            "learned-gate vs plain c-PQ",
     "uneven": "queries/sec at k=100, 10M objects, 16,384 uneven queries in one launch; "
@@ -90,19 +95,50 @@ def measured_traffic(workload: str):
 
 
 def cpu_baseline(values, V, queries, k, budget_s: float, chunk: int = 64):
+    """The oracle's inverted-index search (plain C, one query after another
+    per thread) on the host cores: half the budget on one thread, half on
+    `threads` threads taking chunks of queries from a shared cursor (ctypes
+    calls release the interpreter lock).  Queries are taken from the front of
+    the batch, wrapping around, until the budget is spent."""
+    import threading
     import oracle
     idx = oracle.build_csr(values, V)
     nq = queries.n_queries
-    done, t0 = 0, time.perf_counter()
-    while done < nq and time.perf_counter() - t0 < budget_s:
-        q1 = min(nq, done + chunk)
-        oracle.search_idx(idx, queries, k, done, q1)
-        done = q1
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {nq} queries of the same batch, one thread, "
-                      f"{dt:.1f} s (inverted-index scan + count array + selection, plain C)",
-            "cpu": platform.processor() or platform.machine()}
+
+    def run(threads, budget):
+        state = {"next": 0, "done": 0}
+        lock = threading.Lock()
+        t0 = time.perf_counter()
+
+        def worker():
+            while True:
+                with lock:
+                    if time.perf_counter() - t0 >= budget:
+                        return
+                    q0 = state["next"] % nq
+                    q1 = min(nq, q0 + chunk)
+                    state["next"] += q1 - q0
+                oracle.search_idx(idx, queries, k, q0, q1)
+                with lock:
+                    state["done"] += q1 - q0
+
+        ws = [threading.Thread(target=worker) for _ in range(threads)]
+        for w in ws:
+            w.start()
+        for w in ws:
+            w.join()
+        return state["done"], time.perf_counter() - t0
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    d1, t1 = run(1, budget_s / 2)
+    dn, tn = run(threads, budget_s / 2)
+    return {"value": dn / tn, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": d1 / t1,
+            "sample": f"{dn} queries of the same batch ({nq} queries, taken in order, wrapping "
+                      f"around) on {threads} threads in {tn:.1f} s, and {d1} on one thread in "
+                      f"{t1:.1f} s (inverted-index scan + count array + selection, plain C)",
+            "cpu": platform.processor() or platform.machine(),
+            "host_cpus": os.cpu_count()}
 
 
 def train_gate(genie, torch, ix, sets, epochs: int):
@@ -246,30 +282,70 @@ def line(args, workload, res, config, dtype="u32"):
     return out
 
 
-def bench_relational(args, torch, genie, workloads):
-    inst = workloads.relational()
+def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries, describe,
+                       tune_sample=0, chunk=64):
+    """Relational-style workloads: objects with one value per dim, queries of
+    range items, all resident; `train_queries(rng)` draws the gate's
+    training set over the same objects."""
     nq, k = inst.queries.n_queries, inst.k
     ix = genie.Index(inst.values, inst.V)
     off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
+    tune = None
+    if tune_sample:
+        # scan shape chosen by the autotuner on the batch's first queries
+        from paper_1603_08390_amd.autotune import autotune
+        sq = inst.queries.subset(range(min(nq, tune_sample)))
+        soff, sitems = genie.queries_to_device(sq.q_offsets, sq.items)
+        tune = autotune(ix, soff, sitems, k, sq.max_items(), reps=2)
     sb = SearchBench(genie, torch, ix, nq, k, inst.queries.max_items(), lambda st: (off, items))
     if not args.no_gate:
-        tq = workloads.queries_random_width(np.random.default_rng(workloads.BASE_SEED + 102),
-                                            inst.values, inst.V, args.gate_train_queries)
+        tq = train_queries(np.random.default_rng(workloads.BASE_SEED + 100 + workloads.CONFIG_IDS[name]))
         toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
         sb.model = train_gate(genie, torch, ix, [(toff, titems, tq.max_items(), k)],
                               args.gate_epochs)
     res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]))
-    out = line(args, "relational", res, {
-        "workload": "relational: 1,000,000 objects x 32 dims, per-dim Zipf(1.1) over 256 "
-                    "buckets; 1,024 queries, one range item per dim, width U{0..8}; k=100",
-        "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V, "n_queries": nq, "k": k})
+    cfg = {"workload": describe, "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V,
+           "n_queries": nq, "k": k, "scan_shape": "%dx%d" % tuple(ix.info.scan_shape)}
+    out = line(args, name, res, cfg)
+    if tune is not None:
+        out["autotune_ms"] = tune["ms"]
     if out["learned_gate"]:
         out["learned_gate"].update(train_queries=args.gate_train_queries,
                                    epochs=args.gate_epochs)
-    out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget)
+    out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget,
+                                        chunk=chunk)
                            if not args.no_cpu_baseline and args.cpu_budget > 0 else None)
     ix.free()
     return out
+
+
+def bench_relational(args, torch, genie, workloads):
+    inst = workloads.relational()
+    return bench_item_queries(
+        args, torch, genie, workloads, "relational", inst,
+        lambda rng: workloads.queries_random_width(rng, inst.values, inst.V,
+                                                   args.gate_train_queries),
+        "relational: 1,000,000 objects x 32 dims, per-dim Zipf(1.1) over 256 buckets; 1,024 "
+        "queries, one range item per dim, width U{0..8}; k=100")
+
+
+def bench_tiny(args, torch, genie, workloads):
+    inst = workloads.tiny()
+    return bench_item_queries(
+        args, torch, genie, workloads, "tiny", inst,
+        lambda rng: workloads.queries_halfwidth(rng, inst.values, inst.V,
+                                                args.gate_train_queries, 2),
+        "tiny: 10,000 objects x 16 dims, values uniform in [0,64); 100 queries, one item "
+        "[v-2, v+2] per dim; k=10")
+
+
+def bench_uneven(args, torch, genie, workloads):
+    inst = workloads.uneven()
+    return bench_item_queries(
+        args, torch, genie, workloads, "uneven", inst,
+        lambda rng: workloads.queries_uneven(rng, inst.values, inst.V, args.gate_train_queries),
+        "uneven: 10,000,000 objects x 64 dims, per-dim Zipf(1.1) over 1,024 buckets; 16,384 "
+        "queries of U{4..512} range items in one launch; k=100", tune_sample=1024, chunk=1)
 
 
 def lsh_device(torch, inp):
@@ -368,41 +444,6 @@ def bench_ann(args, torch, genie, workloads):
     return out
 
 
-def bench_uneven(args, torch, genie, workloads):
-    from paper_1603_08390_amd.autotune import autotune
-    inst = workloads.uneven()
-    nq, k = inst.queries.n_queries, inst.k
-    ix = genie.Index(inst.values, inst.V)
-    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
-    max_items = inst.queries.max_items()
-    # scan shape chosen on a sample of the batch (its first 1,024 queries)
-    sq = inst.queries.subset(range(min(nq, 1024)))
-    soff, sitems = genie.queries_to_device(sq.q_offsets, sq.items)
-    tune = autotune(ix, soff, sitems, k, sq.max_items(), reps=2)
-    sb = SearchBench(genie, torch, ix, nq, k, max_items, lambda st: (off, items))
-    if not args.no_gate:
-        rng = np.random.default_rng(workloads.BASE_SEED + 104)
-        tq = workloads.queries_uneven(rng, inst.values, inst.V, args.gate_train_queries)
-        toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
-        sb.model = train_gate(genie, torch, ix, [(toff, titems, tq.max_items(), k)],
-                              args.gate_epochs)
-    res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]))
-    out = line(args, "uneven", res, {
-        "workload": "uneven: 10,000,000 objects x 64 dims, per-dim Zipf(1.1) over 1,024 "
-                    "buckets; 16,384 queries of U{4..512} range items in one launch; k=100",
-        "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V, "n_queries": nq, "k": k,
-        "scan_shape": f"{tune['threads']}x{tune['unroll']}"})
-    out["autotune_ms"] = tune["ms"]
-    if out["learned_gate"]:
-        out["learned_gate"].update(train_queries=args.gate_train_queries,
-                                   epochs=args.gate_epochs)
-    out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget,
-                                        chunk=1)
-                           if not args.no_cpu_baseline and args.cpu_budget > 0 else None)
-    ix.free()
-    return out
-
-
 def bench_serving(args, torch, genie, workloads):
     from paper_1603_08390_amd import serving
     rel = workloads.relational()
@@ -431,6 +472,38 @@ def bench_serving(args, torch, genie, workloads):
     res = {"rel": serving.Resident(rel_ix, rel.queries.max_items(), gate=gates["rel"]),
            "ann": serving.Resident(ann_ix, m, lsh=lsh, gate=gates["ann"])}
 
+    # one group of each (index, k) kind run alone, plain and gated: device
+    # time of the group and the gated search's fallback queries
+    groups = []
+    rng = np.random.default_rng(workloads.BASE_SEED + 109)
+    for target in ("rel", "ann"):
+        for kk_ in ks:
+            g = []
+            for i in range(args.max_batch):
+                if target == "rel":
+                    q = int(rng.integers(0, rel.queries.n_queries))
+                    g.append(serving.Request(i, "rel", kk_, 0.0, items=rel.queries.items_of(q)))
+                else:
+                    q = int(rng.integers(0, inp.queries.shape[0]))
+                    g.append(serving.Request(i, "ann", kk_, 0.0, point=inp.queries[q]))
+            row = {"target": target, "k": kk_, "requests": len(g)}
+            for use_gate in ((False, True) if not args.no_gate else (False,)):
+                ex = serving.GpuExecutor(res, 1, use_gate)
+                for _ in range(2):
+                    ex.launch(0, g)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                reps = 5
+                for _ in range(reps):
+                    h = ex.launch(0, g)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps * 1e3
+                st = genie.workspace_stats(h["ws"])
+                row["gated_ms" if use_gate else "plain_ms"] = round(dt, 3)
+                if use_gate:
+                    row["fallback_queries"] = st["fallback_queries"]
+            groups.append(row)
+
     rng = np.random.default_rng(workloads.BASE_SEED + 107)
     n_req = args.requests
     kind = rng.integers(0, 2, size=n_req)
@@ -451,10 +524,16 @@ def bench_serving(args, torch, genie, workloads):
         return out
 
     def run(arrivals, use_gate):
+        import gc
         srv = serving.Server(res, slots=args.slots, max_batch=args.max_batch, use_gate=use_gate)
-        t0 = time.perf_counter()
-        done = srv.run(requests(arrivals))
-        wall = time.perf_counter() - t0
+        batch = requests(arrivals)
+        gc.collect()
+        gc.disable()
+        try:
+            done = srv.run(batch)
+        finally:
+            gc.enable()
+        wall = max(r.done for r in done)   # the loop's own clock: start -> last completion
         s = serving.latency_summary(done, wall)
         s.update(groups=srv.groups, waited_for_memory=srv.waited_for_memory)
         return {r.rid: r for r in done}, {key: (round(v, 3) if isinstance(v, float) else v)
@@ -473,13 +552,20 @@ def bench_serving(args, torch, genie, workloads):
             g = sat_gate_res[rid]
             if not (np.array_equal(r.ids, g.ids) and np.array_equal(r.counts, g.counts)):
                 raise RuntimeError(f"request {rid}: gated and plain answers differ")
-    rate = 0.7 * sat_plain["qps"]
-    arrivals = serving.poisson_arrivals(np.random.default_rng(workloads.BASE_SEED + 108),
-                                        n_req, rate)
-    _, pois_plain = run(arrivals, False)
-    pois_gate = None
-    if not args.no_gate:
-        _, pois_gate = run(arrivals, True)
+    # Poisson arrivals at fractions of the saturated plain rate, the same
+    # arrival times for the plain and the gated run of each load
+    loads = [float(x) for x in args.loads.split(",")]
+    sweep = []
+    for i, frac in enumerate(loads):
+        rate_i = frac * sat_plain["qps"]
+        arr = serving.poisson_arrivals(np.random.default_rng(workloads.BASE_SEED + 108 + i),
+                                       n_req, rate_i)
+        _, pp = run(arr, False)
+        pg = run(arr, True)[1] if not args.no_gate else None
+        sweep.append({"load": frac, "offered_qps": round(rate_i, 1), "plain": pp,
+                      "learned_gate": pg})
+    head = min(sweep, key=lambda r: abs(r["load"] - 0.7))
+    rate, pois_plain, pois_gate = head["offered_qps"], head["plain"], head["learned_gate"]
     best = pois_gate if pois_gate and pois_gate["qps"] > pois_plain["qps"] else pois_plain
     ms = n_req / best["qps"] * 1e3 if best["qps"] > 0 else 0.0   # the whole request stream
     out = {"metric": METRICS["serving"], "value": best["qps"], "unit": "queries/s",
@@ -488,13 +574,15 @@ def bench_serving(args, torch, genie, workloads):
            "data": "synthetic",
            "config": {"workload": "serving: relational (1M x 32, Zipf(1.1) over 256 buckets) "
                                   "and tau-ANN (1M x 128, 237 LSH functions) requests, 50/50, "
-                                  "k uniform in {10,100,1000}; Poisson arrivals at 0.7x the "
-                                  "saturated plain rate",
+                                  f"k uniform in {{10,100,1000}}; Poisson arrivals at "
+                                  f"{head['load']}x the saturated plain rate",
                       "requests": n_req, "slots": args.slots, "max_batch": args.max_batch,
-                      "offered_qps": round(rate, 1), "parallelism": "single GPU"},
+                      "offered_qps": rate, "parallelism": "single GPU"},
            "saturated": {"plain": sat_plain, "learned_gate": sat_gate,
                          "identical_results": sat_gate is not None},
            "poisson": {"plain": pois_plain, "learned_gate": pois_gate},
+           "load_sweep": sweep,
+           "groups": groups,
            "cpu_baseline": None}
     rel_ix.free()
     ann_ix.free()
@@ -515,9 +603,11 @@ def main():
     ap.add_argument("--no-gate", action="store_true", help="skip the learned-gate path")
     ap.add_argument("--gate-train-queries", type=int, default=4096)
     ap.add_argument("--gate-epochs", type=int, default=30)
-    ap.add_argument("--requests", type=int, default=8192, help="serving: number of requests")
+    ap.add_argument("--requests", type=int, default=50000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: execution slots")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: requests per group")
+    ap.add_argument("--loads", default="0.3,0.5,0.7,0.9",
+                    help="serving: offered loads as fractions of the saturated plain rate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 3 times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -546,8 +636,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
         return
-    fn = {"relational": bench_relational, "ann": bench_ann, "uneven": bench_uneven,
-          "serving": bench_serving}[args.workload]
+    fn = {"relational": bench_relational, "tiny": bench_tiny, "ann": bench_ann,
+          "uneven": bench_uneven, "serving": bench_serving}[args.workload]
     print(json.dumps(fn(args, torch, genie, workloads)), flush=True)
 
 

@@ -79,6 +79,8 @@ typedef struct {
     uint32_t tile_objects;     /* GENIE_TILE_OBJECTS */
     uint64_t n_postings;       /* n_objects * n_dims */
     uint64_t device_bytes;     /* device memory held by the index */
+    uint32_t scan_threads;     /* scan kernel launch shape in use (see */
+    uint32_t scan_unroll;      /* genie_index_set_scan_shape) */
 } genie_index_info;
 
 /*

@@ -60,7 +60,8 @@ class _IndexInfo(ctypes.Structure):
     _fields_ = [("n_objects", ctypes.c_uint64), ("n_dims", ctypes.c_uint32),
                 ("n_buckets", ctypes.c_uint32), ("n_tiles", ctypes.c_uint32),
                 ("tile_objects", ctypes.c_uint32), ("n_postings", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("scan_threads", ctypes.c_uint32),
+                ("scan_unroll", ctypes.c_uint32)]
 
 
 _lib = None
@@ -155,6 +156,7 @@ class IndexInfo:
     tile_objects: int
     n_postings: int
     device_bytes: int
+    scan_shape: tuple      # (threads per workgroup, posting dwords per thread and step)
 
 
 class Index:
@@ -169,10 +171,14 @@ class Index:
         _check(lib.genie_build_index(_np_ptr(values), values.shape[0], values.shape[1],
                                      int(n_buckets), ctypes.byref(h)))
         self._h = h
+        self.refresh_info()
+
+    def refresh_info(self):
         info = _IndexInfo()
-        _check(lib.genie_index_info_get(self._h, ctypes.byref(info)))
+        _check(load().genie_index_info_get(self.handle, ctypes.byref(info)))
         self.info = IndexInfo(info.n_objects, info.n_dims, info.n_buckets, info.n_tiles,
-                              info.tile_objects, info.n_postings, info.device_bytes)
+                              info.tile_objects, info.n_postings, info.device_bytes,
+                              (info.scan_threads, info.scan_unroll))
 
     @property
     def handle(self):
@@ -198,6 +204,7 @@ def genie_build_index(values: np.ndarray, n_buckets: int) -> Index:
 
 def genie_index_set_scan_shape(index: Index, threads: int, unroll: int):
     _check(load().genie_index_set_scan_shape(index.handle, int(threads), int(unroll)))
+    index.refresh_info()
 
 
 SCAN_SHAPES = ((512, 4), (512, 8), (1024, 4), (1024, 8))

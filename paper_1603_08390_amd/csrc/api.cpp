@@ -282,6 +282,8 @@ extern "C" int genie_index_info_get(const genie_index *ix, genie_index_info *out
     out->tile_objects = kTile;
     out->n_postings = ix->n_postings;
     out->device_bytes = ix->device_bytes;
+    out->scan_threads = (uint32_t)ix->scan_threads;
+    out->scan_unroll = (uint32_t)ix->scan_unroll;
     return GENIE_OK;
 }
 

@@ -128,8 +128,8 @@ class GpuExecutor:
             h_cts.copy_(cts, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(st)
-        keep += [off, items, ws, ids, cts]
-        return {"event": ev, "ids": h_ids, "cts": h_cts, "keep": keep}
+        keep += [off, items, ids, cts]
+        return {"event": ev, "ids": h_ids, "cts": h_cts, "ws": ws, "keep": keep}
 
     def done(self, handle) -> bool:
         return handle["event"].query()
@@ -156,15 +156,20 @@ class Server:
 
     def run(self, requests: Sequence[Request], clock=time.perf_counter) -> List[Result]:
         reqs = sorted(requests, key=lambda q: q.arrival)
-        waiting = collections.deque()
+        # waiting requests, one arrival-ordered queue per (index, k); the
+        # oldest head decides which group goes next
+        queues: Dict[tuple, collections.deque] = {}
+        n_waiting = 0
         results: List[Result] = []
         busy = [None] * self.n_slots     # (handle, group, bytes) per slot
         nxt = 0
         t0 = clock()
-        while nxt < len(reqs) or waiting or any(b is not None for b in busy):
+        while nxt < len(reqs) or n_waiting or any(b is not None for b in busy):
             now = clock() - t0
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
-                waiting.append(reqs[nxt])
+                q = reqs[nxt]
+                queues.setdefault((q.target, q.k), collections.deque()).append(q)
+                n_waiting += 1
                 nxt += 1
             for i, b in enumerate(busy):           # completions
                 if b is not None and self.ex.done(b[0]):
@@ -176,24 +181,26 @@ class Server:
                     self.in_use -= b[2]
                     busy[i] = None
             for i in range(self.n_slots):          # admissions
-                if busy[i] is not None or not waiting:
+                if busy[i] is not None or not n_waiting:
                     continue
-                head = waiting[0]
-                key = (head.target, head.k)
-                group = [q for q in waiting if (q.target, q.k) == key][:self.max_batch]
+                key = min((k for k, d in queues.items() if d), key=lambda k: queues[k][0].arrival)
+                dq = queues[key]
+                group = [dq.popleft() for _ in range(min(self.max_batch, len(dq)))]
                 need = self.ex.need_bytes(group)
                 while need > self.budget - self.in_use and len(group) > 1:
-                    group = group[:len(group) // 2]
+                    half = len(group) // 2
+                    dq.extendleft(reversed(group[half:]))
+                    group = group[:half]
                     need = self.ex.need_bytes(group)
                 if need > self.budget - self.in_use:
+                    dq.extendleft(reversed(group))
                     self.waited_for_memory += 1
                     break                          # wait for a running group to finish
-                chosen = set(id(q) for q in group)
-                waiting = collections.deque(q for q in waiting if id(q) not in chosen)
+                n_waiting -= len(group)
                 self.in_use += need
                 self.groups += 1
                 busy[i] = (self.ex.launch(i, group), group, need)
-            if nxt < len(reqs) and not waiting and all(b is None for b in busy):
+            if nxt < len(reqs) and not n_waiting and all(b is None for b in busy):
                 time.sleep(max(0.0, min(0.001, reqs[nxt].arrival - (clock() - t0))))
         return results
 

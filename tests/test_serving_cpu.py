@@ -81,3 +81,16 @@ def test_arrival_order_is_respected():
             for i in range(10)]
     srv.run(reqs)
     assert [rids[0] for _, rids, _, _ in ex.launched] == list(range(9, -1, -1))
+
+
+def test_groups_keep_arrival_order_within_a_key_under_memory_pressure():
+    ex = FakeExecutor(bytes_per_query=100, polls=2)
+    srv = serving.Server(slots=2, max_batch=6, hbm_budget=300, executor=ex)
+    rng = np.random.default_rng(2)
+    reqs = [serving.Request(i, "a" if rng.random() < 0.5 else "b", 1, 0.0,
+                            items=np.zeros((1, 3), np.uint32)) for i in range(50)]
+    res = srv.run(reqs)
+    assert sorted(r.rid for r in res) == list(range(50))
+    for target in ("a", "b"):
+        order = [r for _, rids, t, _ in ex.launched if t == target for r in rids]
+        assert order == sorted(order)
