@@ -19,8 +19,9 @@ Workloads (--workload):
               their exact-match items and searches; recall@100 and the
               approximation ratio against exact l2 are reported.
   uneven      10,000,000 objects x 64 dims, Zipf(1.1) over 1,024 buckets,
-              16,384 queries of 4..512 items in one launch, k = 100; the scan
-              shape is picked by the autotuner first.
+              16,384 queries of 4..512 items in one launch, k = 100; the
+              index tiling and the scan shape are picked by the autotuner
+              first.
   serving     requests mixing the relational and the ANN shapes at k in
               {10, 100, 1000} through the continuous-batching loop: the
               saturated rate (all requests at once), then Poisson arrivals at
@@ -174,10 +175,18 @@ class SearchBench:
         self.ws = genie.alloc_workspace(ix, nq, k)
         self.gids = torch.empty_like(self.ids)
         self.gcts = torch.empty_like(self.ids)
-        self.gws = genie.alloc_workspace(ix, nq, k)
         self.feats = torch.empty((nq, 64), dtype=torch.float32, device="cuda")
         self.pred = torch.empty(nq, dtype=torch.float32, device="cuda")
         self.model = None
+        # the gated path may run on the same objects under another tiling;
+        # each path may have its own scan shape (set before its timed steps)
+        self.plain_shape = None
+        self.gate_shape = None
+        self.set_gate_index(ix)
+
+    def set_gate_index(self, gix):
+        self.gix = gix
+        self.gws = self.genie.alloc_workspace(gix, self.nq, self.k)
 
     def plain_step(self):
         off, items = self.prep(self.stream)
@@ -187,10 +196,10 @@ class SearchBench:
     def gated_step(self):
         g, m = self.genie, self.model
         off, items = self.prep(self.stream)
-        g.genie_gate_features_async(self.ix, off, items, self.k, out=self.feats,
+        g.genie_gate_features_async(self.gix, off, items, self.k, out=self.feats,
                                     stream=self.stream)
         m.predict(self.feats, out=self.pred, stream=self.stream)
-        g.genie_search_gated_async(self.ix, off, items, self.k, self.max_items, self.pred,
+        g.genie_search_gated_async(self.gix, off, items, self.k, self.max_items, self.pred,
                                    m.delta, self.gids, self.gcts, self.gws, self.stream)
 
     def timed(self, step, steps, warmup):
@@ -209,6 +218,8 @@ class SearchBench:
 
     def run(self, steps, warmup, s_total):
         g = self.genie
+        if self.plain_shape:
+            g.genie_index_set_scan_shape(self.ix, *self.plain_shape)
         g.genie_kernel_timing_enable(True)
         g.genie_kernel_timing_read(reset=True)
         el_plain = self.timed(self.plain_step, steps, warmup)
@@ -218,6 +229,8 @@ class SearchBench:
             raise RuntimeError(f"device status {stats}")
         el_gate, gstats, gkt = None, None, None
         if self.model is not None:
+            if self.gate_shape:
+                g.genie_index_set_scan_shape(self.gix, *self.gate_shape)
             el_gate = self.timed(self.gated_step, steps, warmup)
             gkt = g.genie_kernel_timing_read(reset=True)
             gstats = g.workspace_stats(self.gws)
@@ -252,7 +265,9 @@ class SearchBench:
                  "ms_per_step": round(el_plain * 1e3 / steps, 4),
                  "gate_passes_per_step": stats["gate_passes"],
                  "ht_inserts_per_step": stats["ht_inserts"],
-                 "ht_overflow_tiles": stats["ht_overflow_tiles"]}
+                 "ht_overflow_tiles": stats["ht_overflow_tiles"],
+                 "tile_objects": self.ix.info.tile_objects,
+                 "scan_shape": "%dx%d" % tuple(self.ix.info.scan_shape)}
         learned = None
         if el_gate is not None:
             learned = {"value": round(nq * steps / el_gate, 1),
@@ -262,7 +277,9 @@ class SearchBench:
                        "gate_passes_per_step": gstats["gate_passes"],
                        "fallback_queries_per_step": gstats["fallback_queries"],
                        "scan_ms_per_step": round(gkt["scan_ms"] / steps, 4),
-                       "delta": self.model.delta}
+                       "delta": self.model.delta,
+                       "tile_objects": self.gix.info.tile_objects,
+                       "scan_shape": "%dx%d" % tuple(self.gix.info.scan_shape)}
         return {"value": round(nq * steps / elapsed, 1),
                 "ms_per_step": round(elapsed * 1e3 / steps, 4),
                 "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
@@ -288,34 +305,52 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
     range items, all resident; `train_queries(rng)` draws the gate's
     training set over the same objects."""
     nq, k = inst.queries.n_queries, inst.k
-    ix = genie.Index(inst.values, inst.V)
-    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
-    tune = None
+    tune, indexes = None, {}
     if tune_sample:
-        # scan shape chosen by the autotuner on the batch's first queries
-        from paper_1603_08390_amd.autotune import autotune
+        # tiling and scan shape chosen by the autotuner on the batch's first
+        # queries, for each path separately (index builds and tuning are
+        # outside the timed regions)
+        from paper_1603_08390_amd.autotune import tune_tilings
         sq = inst.queries.subset(range(min(nq, tune_sample)))
         soff, sitems = genie.queries_to_device(sq.q_offsets, sq.items)
-        tune = autotune(ix, soff, sitems, k, sq.max_items(), reps=2)
+        indexes = {lg: genie.Index(inst.values, inst.V, lg) for lg in (16, 15)}
+        tune = {"plain": tune_tilings(indexes, soff, sitems, k, sq.max_items(), reps=2)}
+        ix = indexes[tune["plain"]["tile_log2"]]
+    else:
+        ix = genie.Index(inst.values, inst.V)
+    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
     sb = SearchBench(genie, torch, ix, nq, k, inst.queries.max_items(), lambda st: (off, items))
+    if tune:
+        sb.plain_shape = (tune["plain"]["threads"], tune["plain"]["unroll"])
     if not args.no_gate:
         tq = train_queries(np.random.default_rng(workloads.BASE_SEED + 100 + workloads.CONFIG_IDS[name]))
         toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
         sb.model = train_gate(genie, torch, ix, [(toff, titems, tq.max_items(), k)],
                               args.gate_epochs)
+        if tune:
+            pred = sb.model.predict(genie.genie_gate_features_async(ix, soff, sitems, k))
+            tune["gated"] = tune_tilings(indexes, soff, sitems, k, sq.max_items(), reps=2,
+                                         gate=(pred, sb.model.delta))
+            sb.set_gate_index(indexes[tune["gated"]["tile_log2"]])
+            sb.gate_shape = (tune["gated"]["threads"], tune["gated"]["unroll"])
+    for lg, other in indexes.items():
+        if other is not sb.ix and other is not sb.gix:
+            other.free()
     res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]))
     cfg = {"workload": describe, "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V,
-           "n_queries": nq, "k": k, "scan_shape": "%dx%d" % tuple(ix.info.scan_shape)}
+           "n_queries": nq, "k": k}
     out = line(args, name, res, cfg)
     if tune is not None:
-        out["autotune_ms"] = tune["ms"]
+        # per path, per tiling (tile_log2), per scan shape
+        out["autotune_ms"] = {path: t["ms"] for path, t in tune.items()}
     if out["learned_gate"]:
         out["learned_gate"].update(train_queries=args.gate_train_queries,
                                    epochs=args.gate_epochs)
     out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget,
                                         chunk=chunk)
                            if not args.no_cpu_baseline and args.cpu_budget > 0 else None)
-    ix.free()
+    for used in {id(sb.ix): sb.ix, id(sb.gix): sb.gix}.values():
+        used.free()
     return out
 
 

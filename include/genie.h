@@ -54,7 +54,7 @@ extern "C" {
 /* Limits of one search call. */
 #define GENIE_MAX_K 1024          /* results per query */
 #define GENIE_MAX_ITEMS 1024      /* items per query (bounds the count) */
-#define GENIE_TILE_OBJECTS 65535  /* objects per index tile (16-bit local ids, 0xFFFF reserved) */
+#define GENIE_TILE_OBJECTS 65535  /* objects per tile of genie_build_index (16-bit local ids, 0xFFFF reserved) */
 
 /* Device status flags, OR-ed into the first word of a search workspace. */
 #define GENIE_STATUS_BAD_DIM 1u       /* an item named dim >= n_dims (treated as empty) */
@@ -75,8 +75,8 @@ typedef struct {
     uint64_t n_objects;
     uint32_t n_dims;
     uint32_t n_buckets;
-    uint32_t n_tiles;          /* ceil(n_objects / GENIE_TILE_OBJECTS) */
-    uint32_t tile_objects;     /* GENIE_TILE_OBJECTS */
+    uint32_t n_tiles;          /* ceil(n_objects / tile_objects) */
+    uint32_t tile_objects;     /* objects per tile: 2^tile_log2 - 1 */
     uint64_t n_postings;       /* n_objects * n_dims */
     uint64_t device_bytes;     /* device memory held by the index */
     uint32_t scan_threads;     /* scan kernel launch shape in use (see */
@@ -102,6 +102,19 @@ typedef struct {
  */
 int genie_build_index(const uint32_t *values, uint64_t n_objects, uint32_t n_dims,
                       uint32_t n_buckets, genie_index **out);
+
+/*
+ * genie_build_index with tiles of 2^tile_log2 - 1 objects (tile_log2 = 15
+ * or 16; 16 is genie_build_index); the reserved padding id is
+ * 2^tile_log2 - 1.  A search keeps one counter per id of a tile in LDS, so
+ * smaller tiles halve that footprint (16-bit counters: 64 KB instead of
+ * 128 KB, which lets two workgroups share a compute unit) at the price of
+ * twice the tiles, each with its own per-query overhead and candidate list.
+ * Results do not depend on the tiling.  Other arguments and errors as
+ * genie_build_index; GENIE_EINVAL for another tile_log2.
+ */
+int genie_build_index_tiled(const uint32_t *values, uint64_t n_objects, uint32_t n_dims,
+                            uint32_t n_buckets, uint32_t tile_log2, genie_index **out);
 
 /* Free an index and its device memory.  NULL is ignored. */
 void genie_free_index(genie_index *ix);

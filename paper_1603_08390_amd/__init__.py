@@ -34,7 +34,8 @@ STATUS_TOO_MANY_ITEMS = 2
 STATUS_BAD_OFFSETS = 4
 
 EXPORTED = (
-    "genie_build_index", "genie_free_index", "genie_index_info_get", "genie_search",
+    "genie_build_index", "genie_build_index_tiled", "genie_free_index", "genie_index_info_get",
+    "genie_search",
     "genie_search_workspace_size", "genie_search_async", "genie_match_count_async",
     "genie_lsh_signatures", "genie_last_error", "genie_kernel_timing_enable",
     "genie_kernel_timing_read", "genie_search_gated_async", "genie_gate_features_async",
@@ -79,6 +80,8 @@ def load() -> ctypes.CDLL:
     vp, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
     lib.genie_build_index.argtypes = [vp, u64, u32, u32, ctypes.POINTER(vp)]
     lib.genie_build_index.restype = ctypes.c_int
+    lib.genie_build_index_tiled.argtypes = [vp, u64, u32, u32, u32, ctypes.POINTER(vp)]
+    lib.genie_build_index_tiled.restype = ctypes.c_int
     lib.genie_free_index.argtypes = [vp]
     lib.genie_free_index.restype = None
     lib.genie_index_info_get.argtypes = [vp, ctypes.POINTER(_IndexInfo)]
@@ -162,14 +165,16 @@ class IndexInfo:
 class Index:
     """genie_build_index: the inverted index of Section 3.2 on the device."""
 
-    def __init__(self, values: np.ndarray, n_buckets: int):
+    def __init__(self, values: np.ndarray, n_buckets: int, tile_log2: int = 16):
+        """tile_log2: tiles of 2^tile_log2 - 1 objects (15 or 16), see
+        genie_build_index_tiled."""
         values = np.ascontiguousarray(values, dtype=np.uint32)
         if values.ndim != 2:
             raise ValueError("values must be [n_objects, n_dims]")
         lib = load()
         h = ctypes.c_void_p()
-        _check(lib.genie_build_index(_np_ptr(values), values.shape[0], values.shape[1],
-                                     int(n_buckets), ctypes.byref(h)))
+        _check(lib.genie_build_index_tiled(_np_ptr(values), values.shape[0], values.shape[1],
+                                           int(n_buckets), int(tile_log2), ctypes.byref(h)))
         self._h = h
         self.refresh_info()
 
@@ -200,6 +205,10 @@ class Index:
 
 def genie_build_index(values: np.ndarray, n_buckets: int) -> Index:
     return Index(values, n_buckets)
+
+
+def genie_build_index_tiled(values: np.ndarray, n_buckets: int, tile_log2: int) -> Index:
+    return Index(values, n_buckets, tile_log2)
 
 
 def genie_index_set_scan_shape(index: Index, threads: int, unroll: int):

@@ -45,7 +45,8 @@ WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint
     return L;
 }
 
-int search_shape(uint32_t max_items, uint32_t k, int threads, SearchShape *out) {
+int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2,
+                 SearchShape *out) {
     // Counter width b: counts reach at most max_items; one more code (all
     // ones) marks an object already emitted during selection.
     static const int widths[] = {4, 8, 16};
@@ -65,8 +66,9 @@ int search_shape(uint32_t max_items, uint32_t k, int threads, SearchShape *out) 
     while ((1u << lg) < 4u * k)
         lg++;
     const uint32_t cpw = 32 / bits;
-    // static part: the Bitmap Counter (a counter for every 16-bit id)
-    const size_t bc_words = 65536 / cpw;
+    // static part: the Bitmap Counter (a counter for every local id and the
+    // padding id)
+    const size_t bc_words = (size_t(1) << tile_log2) / cpw;
     // dynamic part: misc, HT, ZA, run table, gate queues
     size_t words = 32 + (1u << lg) + (max_items + 2) + 2ull * max_items + 1 +
                    (size_t)(threads / 64) * kGateQueue;
@@ -93,12 +95,23 @@ extern "C" const char *genie_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
                                  genie_index **out) {
+    return genie_build_index_tiled(values, n, d, V, kTileLog2Default, out);
+}
+
+extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
+                                       uint32_t tile_log2, genie_index **out) {
     clear_error();
     if (!values || !out) {
         set_error("null pointer");
         return GENIE_EINVAL;
     }
     *out = nullptr;
+    if (tile_log2 != 15 && tile_log2 != 16) {
+        set_error("tile_log2 must be 15 or 16 (got %u)", tile_log2);
+        return GENIE_EINVAL;
+    }
+    const uint32_t kTile = tile_objects_of(tile_log2);
+    const uint16_t kSentinel = (uint16_t)kTile;
     if (n == 0 || n >= 0xFFFFFFFFull || d == 0 || V == 0 || (uint64_t)d * V >= 0xFFFFFFFFull) {
         set_error("bad sizes n=%llu d=%u V=%u", (unsigned long long)n, d, V);
         return GENIE_EINVAL;
@@ -213,6 +226,8 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
     ix->d = d;
     ix->V = V;
     ix->n_tiles = T;
+    ix->tile_log2 = tile_log2;
+    ix->tile_objects = kTile;
     ix->nkeys = nkeys;
     ix->n_postings = npost;
     ix->stored_postings = stored;
@@ -279,7 +294,7 @@ extern "C" int genie_index_info_get(const genie_index *ix, genie_index_info *out
     out->n_dims = ix->d;
     out->n_buckets = ix->V;
     out->n_tiles = ix->n_tiles;
-    out->tile_objects = kTile;
+    out->tile_objects = ix->tile_objects;
     out->n_postings = ix->n_postings;
     out->device_bytes = ix->device_bytes;
     out->scan_threads = (uint32_t)ix->scan_threads;
@@ -460,7 +475,7 @@ extern "C" int genie_search(const genie_index *ix, const uint64_t *q_offsets,
             return GENIE_EINVAL;
         }
     SearchShape shape;
-    rc = search_shape(max_items, k, ix->scan_threads, &shape);
+    rc = search_shape(max_items, k, ix->scan_threads, ix->tile_log2, &shape);
     if (rc)
         return rc;
 

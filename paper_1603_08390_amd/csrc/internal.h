@@ -8,12 +8,13 @@
 
 #include "genie.h"
 
-// Objects per tile.  Local ids inside a tile fit 16 bits, so postings are
-// stored as uint16 and a tile's counters fit one workgroup's LDS.  The id
-// 0xFFFF is never an object: it pads keyword runs to an even length.
-constexpr uint32_t kTile = GENIE_TILE_OBJECTS;
-static_assert(kTile == 65535, "16-bit local ids with 0xFFFF reserved");
-constexpr uint16_t kSentinel = 0xFFFF;
+// Tiles of 2^L - 1 objects (L = tile_log2, 15 or 16).  Local ids inside a
+// tile fit L bits, so postings are stored as uint16 and a tile's counters
+// (2^L of them) fit one workgroup's LDS.  The id 2^L - 1 is never an
+// object: it pads keyword runs to an even length.
+constexpr uint32_t kTileLog2Default = 16;
+constexpr uint32_t tile_objects_of(uint32_t tile_log2) { return (1u << tile_log2) - 1u; }
+static_assert(tile_objects_of(kTileLog2Default) == GENIE_TILE_OBJECTS, "default tiling");
 constexpr uint64_t kSentinelDwords = 64;   // all-sentinel dwords after each tile's runs
 
 // LDS available to one workgroup on gfx950.
@@ -34,7 +35,9 @@ struct genie_index {
     uint64_t n = 0;          // objects
     uint32_t d = 0;          // dimensions
     uint32_t V = 0;          // buckets (values) per dimension
-    uint32_t n_tiles = 0;    // ceil(n / kTile)
+    uint32_t tile_log2 = kTileLog2Default;
+    uint32_t tile_objects = tile_objects_of(kTileLog2Default);   // also the padding id
+    uint32_t n_tiles = 0;    // ceil(n / tile_objects)
     uint64_t nkeys = 0;      // d * V keywords
     uint64_t n_postings = 0; // n * d
     // device arrays
@@ -81,7 +84,8 @@ struct SearchShape {
     uint32_t ht_log2 = 0;  // hash-table slots = 1 << ht_log2
     size_t lds_bytes = 0;  // dynamic LDS of the scan kernel (the counters are static)
 };
-int search_shape(uint32_t max_items, uint32_t k, int threads, SearchShape *out);
+int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2,
+                 SearchShape *out);
 
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,

@@ -189,25 +189,29 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32
     return before + incl - v;
 }
 
-// Occupancy: with 8- or 4-bit counters the workgroup's LDS (64 or 32 KB of
-// counters plus the gate, queues and table) lets two 1024-thread workgroups
-// share a CU, i.e. 8 waves per SIMD, if the kernel fits 64 VGPRs; the scan
-// is bound by the latency of its loads and LDS atomics, so that occupancy is
-// asked for explicitly.  16-bit counters (128 KB) allow one workgroup per CU.
-template <int BITS, int NT>
+// Occupancy: when the counters take at most 64 KB of LDS (2^LG counters of
+// BITS bits), the workgroup's LDS (counters plus the gate, queues and
+// table) lets two 1024-thread workgroups share a CU, i.e. 8 waves per SIMD,
+// if the kernel fits 64 VGPRs; the scan is bound by the latency of its loads
+// and LDS atomics, so that occupancy is asked for explicitly.  128 KB of
+// counters (16-bit counters over 2^16 ids) allow one workgroup per CU.
+template <int BITS, int NT, int LG>
 constexpr int scan_waves_per_eu() {
-    return (NT == 1024 && BITS != 16) ? 8 : 1;
+    return (NT == 1024 && (BITS << LG) <= (8 << 16)) ? 8 : 1;
 }
 
-template <int BITS, int NT, int U, bool DUMP>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<BITS, NT>())))
+template <int BITS, int NT, int U, bool DUMP, int LG>
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<BITS, NT, LG>())))
 void scan_cpq_kernel(ScanParams p) {
     static_assert(BITS == 4 || BITS == 8 || BITS == 16, "power-of-two counter width");
     constexpr uint32_t CPW = 32 / BITS;                   // counters per word
     constexpr uint32_t LCPW = BITS == 4 ? 3 : (BITS == 8 ? 2 : 1);   // log2(CPW)
     constexpr uint32_t LBITS = BITS == 4 ? 2 : (BITS == 8 ? 3 : 4);  // log2(BITS)
     constexpr uint32_t MASK = (1u << BITS) - 1;           // also the "emitted" mark
-    constexpr uint32_t NW = 65536 / CPW;                  // a counter for every 16-bit id
+    constexpr uint32_t TILE = (1u << LG) - 1;             // objects per tile
+    constexpr uint32_t SENT = TILE;                       // the padding id
+    constexpr uint32_t NW = (1u << LG) / CPW;             // a counter for every LG-bit id
     constexpr uint32_t NWAVE = NT / 64;
     constexpr uint32_t CH = 64 * U;                       // dwords per wave per step
 
@@ -241,8 +245,8 @@ void scan_cpq_kernel(ScanParams p) {
     const uint32_t q = p.qlist ? p.qlist[qrow] : qrow;
     const uint32_t tid = threadIdx.x;
 
-    const uint64_t tile0 = (uint64_t)t * kTile;
-    const uint32_t tile_n = (uint32_t)min<uint64_t>(kTile, p.n - tile0);
+    const uint64_t tile0 = (uint64_t)t * TILE;
+    const uint32_t tile_n = (uint32_t)min<uint64_t>(TILE, p.n - tile0);
     const uint64_t i0 = p.q_off[q], i1 = p.q_off[q + 1];
     const bool bad_offsets = i1 < i0 || i1 > p.n_items;
     const uint64_t s64 = bad_offsets ? 0 : i1 - i0;
@@ -329,7 +333,7 @@ void scan_cpq_kernel(ScanParams p) {
     // neighbouring lanes touch ascend together and spread over neighbouring
     // LDS banks.  The run cursor is the same in every lane: a piece inside
     // one run is addressed as cursor + lane.  Runs are padded with the
-    // reserved id 0xFFFF, whose counter is a dummy (the top field of the
+    // reserved padding id 2^LG - 1, whose counter is a dummy (the top field of the
     // last word, where carries fall off), so every element is counted
     // without a bounds test; lanes past the end read the tile's trailing
     // all-sentinel dwords.
@@ -429,7 +433,7 @@ void scan_cpq_kernel(ScanParams p) {
                 for (int h = 0; h < 2; h++) {
                     const uint32_t lid = h ? (v[u] >> 16) : (v[u] & 0xFFFFu);
                     const uint32_t val = f[2 * u + h] + 1;
-                    const bool pass = val >= at_reg && lid != kSentinel;
+                    const bool pass = val >= at_reg && lid != SENT;
                     const uint64_t m = __ballot(pass);
                     if (m) {
                         passes += (uint32_t)__popcll(m);
@@ -648,9 +652,9 @@ __global__ void clear_status_kernel(uint32_t *status) {
         status[threadIdx.x] = 0;
 }
 
-template <int BITS, int NT, int U>
+template <int BITS, int NT, int U, int LG>
 int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipStream_t st) {
-    auto kern = dump ? scan_cpq_kernel<BITS, NT, U, true> : scan_cpq_kernel<BITS, NT, U, false>;
+    auto kern = dump ? scan_cpq_kernel<BITS, NT, U, true, LG> : scan_cpq_kernel<BITS, NT, U, false, LG>;
     GENIE_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds));
     void *ev = timing_begin(st);
@@ -660,24 +664,34 @@ int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipS
     return GENIE_OK;
 }
 
-template <int BITS>
+template <int BITS, int LG>
 int dispatch_shape(int nt, int u, const ScanParams &sp, bool dump, size_t lds, uint64_t grid,
                    hipStream_t st) {
-    if (nt == 512 && u == 4) return launch_scan<BITS, 512, 4>(sp, dump, lds, grid, st);
-    if (nt == 512 && u == 8) return launch_scan<BITS, 512, 8>(sp, dump, lds, grid, st);
-    if (nt == 1024 && u == 4) return launch_scan<BITS, 1024, 4>(sp, dump, lds, grid, st);
-    if (nt == 1024 && u == 8) return launch_scan<BITS, 1024, 8>(sp, dump, lds, grid, st);
+    if (nt == 512 && u == 4) return launch_scan<BITS, 512, 4, LG>(sp, dump, lds, grid, st);
+    if (nt == 512 && u == 8) return launch_scan<BITS, 512, 8, LG>(sp, dump, lds, grid, st);
+    if (nt == 1024 && u == 4) return launch_scan<BITS, 1024, 4, LG>(sp, dump, lds, grid, st);
+    if (nt == 1024 && u == 8) return launch_scan<BITS, 1024, 8, LG>(sp, dump, lds, grid, st);
     set_error("no scan kernel for %d threads x %d dwords", nt, u);
     return GENIE_EINVAL;
 }
 
-int dispatch_scan(int bits, int nt, int u, const ScanParams &sp, bool dump, size_t lds,
+template <int LG>
+int dispatch_bits(int bits, int nt, int u, const ScanParams &sp, bool dump, size_t lds,
                   uint64_t grid, hipStream_t st) {
     switch (bits) {
-    case 4: return dispatch_shape<4>(nt, u, sp, dump, lds, grid, st);
-    case 8: return dispatch_shape<8>(nt, u, sp, dump, lds, grid, st);
-    case 16: return dispatch_shape<16>(nt, u, sp, dump, lds, grid, st);
+    case 4: return dispatch_shape<4, LG>(nt, u, sp, dump, lds, grid, st);
+    case 8: return dispatch_shape<8, LG>(nt, u, sp, dump, lds, grid, st);
+    case 16: return dispatch_shape<16, LG>(nt, u, sp, dump, lds, grid, st);
     default: set_error("no kernel for %d-bit counters", bits); return GENIE_ERANGE;
+    }
+}
+
+int dispatch_scan(int bits, int nt, int u, uint32_t tile_log2, const ScanParams &sp, bool dump,
+                  size_t lds, uint64_t grid, hipStream_t st) {
+    switch (tile_log2) {
+    case 15: return dispatch_bits<15>(bits, nt, u, sp, dump, lds, grid, st);
+    case 16: return dispatch_bits<16>(bits, nt, u, sp, dump, lds, grid, st);
+    default: set_error("no kernel for tiles of 2^%u - 1 objects", tile_log2); return GENIE_ERANGE;
     }
 }
 
@@ -696,7 +710,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
         return GENIE_EINVAL;
     }
     SearchShape shape;
-    int rc = search_shape(max_items, k, ix->scan_threads, &shape);
+    int rc = search_shape(max_items, k, ix->scan_threads, ix->tile_log2, &shape);
     if (rc)
         return rc;
     char *ws = static_cast<char *>(d_workspace);
@@ -732,8 +746,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     }
     hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, stream, sp.status);
     GENIE_HIP(hipGetLastError());
-    rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, sp, dump, shape.lds_bytes,
-                       grid, stream);
+    rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, ix->tile_log2, sp, dump,
+                       shape.lds_bytes, grid, stream);
     if (rc || dump)
         return rc;
     MergeParams mp{};
@@ -762,8 +776,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     fp.gate = nullptr;
     fp.qlist = fb_list;
     fp.qcount = fb_count;
-    rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, fp, false, shape.lds_bytes,
-                       grid, stream);
+    rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, ix->tile_log2, fp, false,
+                       shape.lds_bytes, grid, stream);
     if (rc)
         return rc;
     MergeParams fm = mp;

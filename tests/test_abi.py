@@ -55,6 +55,11 @@ def test_argument_errors_without_device():
     bad = np.array([[0, 5]], dtype=np.uint32)
     assert lib.genie_build_index(bad.ctypes.data, 1, 2, 3, ctypes.byref(out)) == genie.GENIE_EINVAL
     assert b"n_buckets" in lib.genie_last_error()
+    # tiles other than 2^15 - 1 or 2^16 - 1 objects are refused
+    for lg in (0, 14, 17):
+        assert lib.genie_build_index_tiled(vals.ctypes.data, 4, 2, 3, lg,
+                                           ctypes.byref(out)) == genie.GENIE_EINVAL
+        assert b"tile_log2" in lib.genie_last_error()
     # search on a null index, bad k
     ids = np.zeros(4, dtype=np.uint32)
     off = np.array([0, 0], dtype=np.uint64)

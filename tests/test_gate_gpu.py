@@ -117,10 +117,10 @@ def _plain_and_gated(ix, queries, k, gate, delta):
             genie.as_uint32(b_ids), genie.as_uint32(b_cts), genie.workspace_stats(ws_b))
 
 
-@pytest.mark.parametrize("k", [10, 100])
-def test_gated_search_is_exact(k):
+@pytest.mark.parametrize("k,tile_log2", [(10, 16), (100, 16), (100, 15)])
+def test_gated_search_is_exact(k, tile_log2):
     inst = workloads.relational(n=3 * 65535 + 99, d=12, V=48, nq=64, k=k)
-    ix = genie.Index(inst.values, inst.V)
+    ix = genie.Index(inst.values, inst.V, tile_log2)
     oidx = oracle.build_csr(inst.values, inst.V)
     o_ids, o_cts, kth, _ = oracle.search_idx(oidx, inst.queries, k)
     rng = np.random.default_rng(k)

@@ -25,10 +25,10 @@ def _run(ix, queries, k, stream=None):
     return genie.as_uint32(ids), genie.as_uint32(cts), genie.workspace_stats(ws)
 
 
-def _check(values, V, queries, k, ix=None, qs=None):
+def _check(values, V, queries, k, ix=None, qs=None, tile_log2=16):
     own = ix is None
     if own:
-        ix = genie.Index(values, V)
+        ix = genie.Index(values, V, tile_log2)
     ids, cts, st = _run(ix, queries, k)
     assert st["status"] == 0, st
     oidx = oracle.build_csr(values, V)
@@ -98,9 +98,33 @@ def test_edge_cases():
     _check(same, 4, q2, 100)
 
 
-def test_match_count_dump_equals_oracle():
+# Tiles of 2^15 - 1 objects: the same answers with every counter width
+# (4-bit: <= 14 items, 8-bit: <= 254, 16-bit: more), ragged last tiles and
+# ties across tiles.
+@pytest.mark.parametrize("case", ["bits4", "bits8", "bits16", "ties"])
+def test_smaller_tiles(case):
+    print("tile_log2 15", case, flush=True)
+    if case == "bits4":
+        inst = workloads.relational(n=4 * 32767 + 5, d=12, V=16, nq=30, k=10)
+        _check(inst.values, inst.V, inst.queries, 10, tile_log2=15)
+    elif case == "bits8":
+        inst = workloads.relational(n=5 * 32767 + 321, d=24, V=40, nq=40, k=100)
+        _check(inst.values, inst.V, inst.queries, 100, tile_log2=15)
+    elif case == "bits16":
+        inst = workloads.uneven(n=100_000, d=16, V=64, nq=24, smin=200, smax=400)
+        _check(inst.values, inst.V, inst.queries, 100, tile_log2=15)
+    else:
+        same = np.full((3 * 32767 + 9, 3), 2, dtype=np.uint32)
+        q2 = workloads.Queries(np.array([0, 3], np.uint64),
+                               np.array([[0, 2, 2], [1, 0, 3], [2, 3, 3]], np.uint32))
+        _check(same, 4, q2, 1000, tile_log2=15)
+
+
+@pytest.mark.parametrize("tile_log2", [16, 15])
+def test_match_count_dump_equals_oracle(tile_log2):
     inst = workloads.relational(n=2 * 65536 + 77, d=12, V=48, nq=6)
-    ix = genie.Index(inst.values, inst.V)
+    ix = genie.Index(inst.values, inst.V, tile_log2)
+    assert ix.info.tile_objects == (1 << tile_log2) - 1
     off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
     counts, ws = genie.genie_match_count_async(ix, off, items, inst.queries.max_items())
     torch.cuda.synchronize()

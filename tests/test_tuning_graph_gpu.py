@@ -34,6 +34,29 @@ def test_autotune_shapes_agree_and_best_is_set(tmp_path):
     ix.free()
 
 
+def test_autotune_index_picks_a_tiling(tmp_path):
+    inst = workloads.uneven(n=70_000, d=16, V=64, nq=32, smin=100, smax=300)
+    cache = str(tmp_path / "tune.json")
+    ix, rep = autotune.autotune_index(inst.values, inst.V, inst.queries.q_offsets,
+                                      inst.queries.items, 50, inst.queries.max_items(), reps=2,
+                                      cache_path=cache, key="uneven-small")
+    assert set(rep["ms"]) == {"16", "15"}
+    assert ix.info.tile_objects == (1 << rep["tile_log2"]) - 1
+    assert ix.info.scan_shape == (rep["threads"], rep["unroll"])
+    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
+    ids, cts, _ = genie.genie_search_async(ix, off, items, 50, inst.queries.max_items())
+    o_ids, o_cts, _, _ = oracle.search_idx(oracle.build_csr(inst.values, inst.V),
+                                           inst.queries, 50)
+    assert np.array_equal(genie.as_uint32(ids), o_ids)
+    assert np.array_equal(genie.as_uint32(cts), o_cts)
+    ix.free()
+    ix2, rep2 = autotune.autotune_index(inst.values, inst.V, inst.queries.q_offsets,
+                                        inst.queries.items, 50, inst.queries.max_items(),
+                                        cache_path=cache, key="uneven-small")
+    assert rep2["cached"] and ix2.info.tile_objects == (1 << rep["tile_log2"]) - 1
+    ix2.free()
+
+
 def test_graph_replays_match_eager():
     inst = workloads.relational(n=2 * 65535 + 5, d=12, V=48, nq=200)
     ix = genie.Index(inst.values, inst.V)
