@@ -219,7 +219,8 @@ class SearchBench:
     def run(self, steps, warmup, s_total):
         g = self.genie
         if self.plain_shape:
-            g.genie_index_set_scan_shape(self.ix, *self.plain_shape)
+            g.genie_index_set_scan_shape(self.ix, *self.plain_shape[:2])
+            g.genie_index_set_scan_schedule(self.ix, self.plain_shape[2])
         g.genie_kernel_timing_enable(True)
         g.genie_kernel_timing_read(reset=True)
         el_plain = self.timed(self.plain_step, steps, warmup)
@@ -230,7 +231,8 @@ class SearchBench:
         el_gate, gstats, gkt = None, None, None
         if self.model is not None:
             if self.gate_shape:
-                g.genie_index_set_scan_shape(self.gix, *self.gate_shape)
+                g.genie_index_set_scan_shape(self.gix, *self.gate_shape[:2])
+                g.genie_index_set_scan_schedule(self.gix, self.gate_shape[2])
             el_gate = self.timed(self.gated_step, steps, warmup)
             gkt = g.genie_kernel_timing_read(reset=True)
             gstats = g.workspace_stats(self.gws)
@@ -267,7 +269,8 @@ class SearchBench:
                  "ht_inserts_per_step": stats["ht_inserts"],
                  "ht_overflow_tiles": stats["ht_overflow_tiles"],
                  "tile_objects": self.ix.info.tile_objects,
-                 "scan_shape": "%dx%d" % tuple(self.ix.info.scan_shape)}
+                 "scan_shape": "%dx%d" % tuple(self.ix.info.scan_shape),
+                 "schedule": "persistent" if self.ix.info.scan_persistent else "grid"}
         learned = None
         if el_gate is not None:
             learned = {"value": round(nq * steps / el_gate, 1),
@@ -279,7 +282,8 @@ class SearchBench:
                        "scan_ms_per_step": round(gkt["scan_ms"] / steps, 4),
                        "delta": self.model.delta,
                        "tile_objects": self.gix.info.tile_objects,
-                       "scan_shape": "%dx%d" % tuple(self.gix.info.scan_shape)}
+                       "scan_shape": "%dx%d" % tuple(self.gix.info.scan_shape),
+                       "schedule": "persistent" if self.gix.info.scan_persistent else "grid"}
         return {"value": round(nq * steps / elapsed, 1),
                 "ms_per_step": round(elapsed * 1e3 / steps, 4),
                 "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
@@ -321,7 +325,8 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
     off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
     sb = SearchBench(genie, torch, ix, nq, k, inst.queries.max_items(), lambda st: (off, items))
     if tune:
-        sb.plain_shape = (tune["plain"]["threads"], tune["plain"]["unroll"])
+        sb.plain_shape = (tune["plain"]["threads"], tune["plain"]["unroll"],
+                          tune["plain"]["persistent"])
     if not args.no_gate:
         tq = train_queries(np.random.default_rng(workloads.BASE_SEED + 100 + workloads.CONFIG_IDS[name]))
         toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
@@ -332,7 +337,8 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
             tune["gated"] = tune_tilings(indexes, soff, sitems, k, sq.max_items(), reps=2,
                                          gate=(pred, sb.model.delta))
             sb.set_gate_index(indexes[tune["gated"]["tile_log2"]])
-            sb.gate_shape = (tune["gated"]["threads"], tune["gated"]["unroll"])
+            sb.gate_shape = (tune["gated"]["threads"], tune["gated"]["unroll"],
+                             tune["gated"]["persistent"])
     for lg, other in indexes.items():
         if other is not sb.ix and other is not sb.gix:
             other.free()

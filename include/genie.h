@@ -81,6 +81,7 @@ typedef struct {
     uint64_t device_bytes;     /* device memory held by the index */
     uint32_t scan_threads;     /* scan kernel launch shape in use (see */
     uint32_t scan_unroll;      /* genie_index_set_scan_shape) */
+    uint32_t scan_persistent;  /* schedule (genie_index_set_scan_schedule) */
 } genie_index_info;
 
 /*
@@ -128,6 +129,19 @@ void genie_free_index(genie_index *ix);
  * Errors: GENIE_EINVAL.
  */
 int genie_index_set_scan_shape(genie_index *ix, uint32_t threads, uint32_t unroll);
+
+/*
+ * Schedule of the scan kernel for searches on this index.  0 (the
+ * default): one workgroup per (query, tile) pair, the hardware dispatcher
+ * hands pairs to compute units as workgroups finish.  1: persistent
+ * workgroups, as many as fit the device at once, each taking pairs from its
+ * XCD's slice of the pair list through a device counter and then helping
+ * the other slices (Section 3.2.1's load balancing: work goes to whichever
+ * workgroup is free).  Results do not depend on it; speed may (the
+ * autotuner picks it).  Not to be changed while a search on the index is
+ * being enqueued.  Errors: GENIE_EINVAL.
+ */
+int genie_index_set_scan_schedule(genie_index *ix, uint32_t persistent);
 
 /* Describe an index.  Errors: GENIE_EINVAL. */
 int genie_index_info_get(const genie_index *ix, genie_index_info *out);

@@ -41,6 +41,7 @@ EXPORTED = (
     "genie_kernel_timing_read", "genie_search_gated_async", "genie_gate_features_async",
     "genie_gate_forward_async", "genie_gate_workspace_size", "genie_gate_backward_async",
     "genie_gate_adam_async", "genie_lsh_items_async", "genie_index_set_scan_shape",
+    "genie_index_set_scan_schedule",
 )
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
@@ -62,7 +63,7 @@ class _IndexInfo(ctypes.Structure):
                 ("n_buckets", ctypes.c_uint32), ("n_tiles", ctypes.c_uint32),
                 ("tile_objects", ctypes.c_uint32), ("n_postings", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("scan_threads", ctypes.c_uint32),
-                ("scan_unroll", ctypes.c_uint32)]
+                ("scan_unroll", ctypes.c_uint32), ("scan_persistent", ctypes.c_uint32)]
 
 
 _lib = None
@@ -119,6 +120,8 @@ def load() -> ctypes.CDLL:
     lib.genie_lsh_items_async.restype = ctypes.c_int
     lib.genie_index_set_scan_shape.argtypes = [vp, u32, u32]
     lib.genie_index_set_scan_shape.restype = ctypes.c_int
+    lib.genie_index_set_scan_schedule.argtypes = [vp, u32]
+    lib.genie_index_set_scan_schedule.restype = ctypes.c_int
     lib.genie_last_error.argtypes = []
     lib.genie_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -160,6 +163,7 @@ class IndexInfo:
     n_postings: int
     device_bytes: int
     scan_shape: tuple      # (threads per workgroup, posting dwords per thread and step)
+    scan_persistent: int   # 0: one workgroup per (query, tile) pair; 1: persistent
 
 
 class Index:
@@ -183,7 +187,7 @@ class Index:
         _check(load().genie_index_info_get(self.handle, ctypes.byref(info)))
         self.info = IndexInfo(info.n_objects, info.n_dims, info.n_buckets, info.n_tiles,
                               info.tile_objects, info.n_postings, info.device_bytes,
-                              (info.scan_threads, info.scan_unroll))
+                              (info.scan_threads, info.scan_unroll), info.scan_persistent)
 
     @property
     def handle(self):
@@ -216,7 +220,13 @@ def genie_index_set_scan_shape(index: Index, threads: int, unroll: int):
     index.refresh_info()
 
 
+def genie_index_set_scan_schedule(index: Index, persistent: int):
+    _check(load().genie_index_set_scan_schedule(index.handle, int(persistent)))
+    index.refresh_info()
+
+
 SCAN_SHAPES = ((512, 4), (512, 8), (1024, 4), (1024, 8))
+SCAN_SCHEDULES = (0, 1)   # one workgroup per pair, persistent
 
 
 def genie_search(index: Index, q_offsets: np.ndarray, items: np.ndarray, k: int

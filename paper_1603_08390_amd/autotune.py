@@ -1,10 +1,11 @@
 """Autotuner for the index tiling and the scan kernel's launch shape.
 
 `autotune`: for one index and a sample batch of its queries, every compiled
-shape (threads per workgroup x posting dwords per thread and step) runs the
-search a few times; the answers must be identical across shapes (they are a
-function of the queries alone) and the fastest shape, by HIP-event time on
-the search stream, is set on the index.
+shape (threads per workgroup x posting dwords per thread and step) under
+each schedule (one workgroup per pair, or persistent workgroups over a pair
+queue) runs the search a few times; the answers must be identical across
+them (they are a function of the queries alone) and the fastest, by
+HIP-event time on the search stream, is set on the index.
 
 `autotune_index`: builds the index with each tiling (tiles of 2^15 - 1 or
 2^16 - 1 objects), tunes the shape on each, requires identical answers
@@ -19,24 +20,32 @@ import json
 import os
 from typing import Optional
 
-from . import (SCAN_SHAPES, Index, alloc_workspace, genie_index_set_scan_shape,
-               genie_search_async, genie_search_gated_async, queries_to_device)
+from . import (SCAN_SCHEDULES, SCAN_SHAPES, Index, alloc_workspace,
+               genie_index_set_scan_schedule, genie_index_set_scan_shape, genie_search_async,
+               genie_search_gated_async, queries_to_device)
+
+
+def _label(nt, u, sched):
+    return f"{nt}x{u}" + ("p" if sched else "")
+
+
+def _apply(index, nt, u, sched):
+    genie_index_set_scan_shape(index, nt, u)
+    genie_index_set_scan_schedule(index, sched)
 
 
 def autotune(index, d_q_offsets, d_items, k: int, max_items: int, reps: int = 5,
-             shapes=SCAN_SHAPES, cache_path: Optional[str] = None,
+             shapes=SCAN_SHAPES, schedules=SCAN_SCHEDULES, cache_path: Optional[str] = None,
              key: Optional[str] = None, gate=None) -> dict:
-    """gate: None to tune the plain search, or (d_pred, delta) to tune the
-    gated search with those per-query predictions."""
+    """Every (shape, schedule) on one index.  gate: None to tune the plain
+    search, or (d_pred, delta) to tune the gated search with those per-query
+    predictions.  Timings are keyed "threads x unroll", with a trailing "p"
+    for the persistent schedule."""
     import torch
-    dev_name = torch.cuda.get_device_name()
-    if cache_path and key and os.path.exists(cache_path):
-        with open(cache_path) as f:
-            cache = json.load(f)
-        hit = cache.get(f"{key}|{dev_name}")
-        if hit:
-            genie_index_set_scan_shape(index, hit["threads"], hit["unroll"])
-            return dict(hit, cached=True)
+    hit = _cache_get(cache_path, key)
+    if hit:
+        _apply(index, hit["threads"], hit["unroll"], hit.get("persistent", 0))
+        return dict(hit, cached=True)
     nq = d_q_offsets.numel() - 1
     ws = alloc_workspace(index, nq, k)
     ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
@@ -50,35 +59,29 @@ def autotune(index, d_q_offsets, d_items, k: int, max_items: int, reps: int = 5,
                                      gate[1], ids, cts, ws)
 
     ref = None
-    times = {}
-    for (nt, u) in shapes:
-        genie_index_set_scan_shape(index, nt, u)
-        search()
-        torch.cuda.synchronize()
-        if ref is None:
-            ref = (ids.clone(), cts.clone())
-        elif not (torch.equal(ref[0], ids) and torch.equal(ref[1], cts)):
-            raise RuntimeError(f"scan shape {nt}x{u} changed the answers")
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+    times, configs = {}, {}
+    for sched in schedules:
+        for (nt, u) in shapes:
+            _apply(index, nt, u, sched)
             search()
-        e1.record()
-        torch.cuda.synchronize()
-        times[f"{nt}x{u}"] = e0.elapsed_time(e1) / reps
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = (ids.clone(), cts.clone())
+            elif not (torch.equal(ref[0], ids) and torch.equal(ref[1], cts)):
+                raise RuntimeError(f"scan shape {_label(nt, u, sched)} changed the answers")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                search()
+            e1.record()
+            torch.cuda.synchronize()
+            times[_label(nt, u, sched)] = e0.elapsed_time(e1) / reps
+            configs[_label(nt, u, sched)] = (nt, u, sched)
     best = min(times, key=times.get)
-    nt, u = (int(x) for x in best.split("x"))
-    genie_index_set_scan_shape(index, nt, u)
-    out = {"threads": nt, "unroll": u, "ms": times, "cached": False}
-    if cache_path and key:
-        cache = {}
-        if os.path.exists(cache_path):
-            with open(cache_path) as f:
-                cache = json.load(f)
-        cache[f"{key}|{dev_name}"] = {"threads": nt, "unroll": u, "ms": times}
-        with open(cache_path, "w") as f:
-            json.dump(cache, f, indent=1)
-    return out
+    nt, u, sched = configs[best]
+    _apply(index, nt, u, sched)
+    _cache_put(cache_path, key, {"threads": nt, "unroll": u, "persistent": sched, "ms": times})
+    return {"threads": nt, "unroll": u, "persistent": sched, "ms": times, "cached": False}
 
 
 def _cache_get(cache_path, key):
@@ -103,7 +106,8 @@ def _cache_put(cache_path, key, value):
 
 
 def tune_tilings(indexes: dict, d_q_offsets, d_items, k: int, max_items: int,
-                 shapes=SCAN_SHAPES, reps: int = 3, gate=None) -> dict:
+                 shapes=SCAN_SHAPES, schedules=SCAN_SCHEDULES, reps: int = 3,
+                 gate=None) -> dict:
     """Tune the scan shape on every index of {tile_log2: Index} (the same
     objects under different tilings) for one path (plain, or gated with
     gate = (d_pred, delta)); the answers must agree across tilings.  Every
@@ -114,7 +118,7 @@ def tune_tilings(indexes: dict, d_q_offsets, d_items, k: int, max_items: int,
     ref, best, report = None, None, {}
     for lg, ix in indexes.items():
         res = autotune(ix, d_q_offsets, d_items, k, max_items, reps=reps, shapes=shapes,
-                       gate=gate)
+                       schedules=schedules, gate=gate)
         if gate is None:
             ids, cts, _ = genie_search_async(ix, d_q_offsets, d_items, k, max_items)
         else:
@@ -128,14 +132,14 @@ def tune_tilings(indexes: dict, d_q_offsets, d_items, k: int, max_items: int,
         ms = min(res["ms"].values())
         report[str(lg)] = res["ms"]
         if best is None or ms < best[1]:
-            best = (lg, ms, res["threads"], res["unroll"])
-    lg, ms, nt, u = best
-    return {"tile_log2": lg, "threads": nt, "unroll": u, "ms": report, "queries": nq,
-            "path": "plain" if gate is None else "gated"}
+            best = (lg, ms, res["threads"], res["unroll"], res["persistent"])
+    lg, ms, nt, u, sched = best
+    return {"tile_log2": lg, "threads": nt, "unroll": u, "persistent": sched, "ms": report,
+            "queries": nq, "path": "plain" if gate is None else "gated"}
 
 
 def autotune_index(values, n_buckets: int, q_offsets, items, k: int, max_items: int,
-                   tilings=(16, 15), shapes=SCAN_SHAPES, reps: int = 3,
+                   tilings=(16, 15), shapes=SCAN_SHAPES, schedules=SCAN_SCHEDULES, reps: int = 3,
                    cache_path: Optional[str] = None, key: Optional[str] = None):
     """Build the index with the fastest tiling and scan shape for the plain
     search of a sample batch (host q_offsets / items).  Returns (index,
@@ -143,12 +147,13 @@ def autotune_index(values, n_buckets: int, q_offsets, items, k: int, max_items: 
     hit = _cache_get(cache_path, key)
     if hit:
         ix = Index(values, n_buckets, hit["tile_log2"])
-        genie_index_set_scan_shape(ix, hit["threads"], hit["unroll"])
+        _apply(ix, hit["threads"], hit["unroll"], hit.get("persistent", 0))
         return ix, dict(hit, cached=True)
     off, it = queries_to_device(q_offsets, items)
     indexes = {lg: Index(values, n_buckets, lg) for lg in tilings}
     try:
-        rep = tune_tilings(indexes, off, it, k, max_items, shapes=shapes, reps=reps)
+        rep = tune_tilings(indexes, off, it, k, max_items, shapes=shapes, schedules=schedules,
+                           reps=reps)
     except Exception:
         for ix in indexes.values():
             ix.free()
@@ -157,5 +162,5 @@ def autotune_index(values, n_buckets: int, q_offsets, items, k: int, max_items: 
         if lg != rep["tile_log2"]:
             ix.free()
     _cache_put(cache_path, key, {"tile_log2": rep["tile_log2"], "threads": rep["threads"],
-                                 "unroll": rep["unroll"]})
+                                 "unroll": rep["unroll"], "persistent": rep["persistent"]})
     return indexes[rep["tile_log2"]], dict(rep, cached=False)

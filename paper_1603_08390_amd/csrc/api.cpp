@@ -67,8 +67,8 @@ int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2
         lg++;
     const uint32_t cpw = 32 / bits;
     // static part: the Bitmap Counter (a counter for every local id and the
-    // padding id)
-    const size_t bc_words = (size_t(1) << tile_log2) / cpw;
+    // padding id) and one word of the persistent schedule
+    const size_t bc_words = (size_t(1) << tile_log2) / cpw + 1;
     // dynamic part: misc, HT, ZA, run table, gate queues
     size_t words = 32 + (1u << lg) + (max_items + 2) + 2ull * max_items + 1 +
                    (size_t)(threads / 64) * kGateQueue;
@@ -284,6 +284,16 @@ extern "C" int genie_index_set_scan_shape(genie_index *ix, uint32_t threads, uin
     return GENIE_OK;
 }
 
+extern "C" int genie_index_set_scan_schedule(genie_index *ix, uint32_t persistent) {
+    clear_error();
+    if (!ix || persistent > 1) {
+        set_error("scan schedule must be 0 (one workgroup per pair) or 1 (persistent)");
+        return GENIE_EINVAL;
+    }
+    ix->scan_persistent = (int)persistent;
+    return GENIE_OK;
+}
+
 extern "C" int genie_index_info_get(const genie_index *ix, genie_index_info *out) {
     clear_error();
     if (!ix || !out) {
@@ -299,6 +309,7 @@ extern "C" int genie_index_info_get(const genie_index *ix, genie_index_info *out
     out->device_bytes = ix->device_bytes;
     out->scan_threads = (uint32_t)ix->scan_threads;
     out->scan_unroll = (uint32_t)ix->scan_unroll;
+    out->scan_persistent = (uint32_t)ix->scan_persistent;
     return GENIE_OK;
 }
 

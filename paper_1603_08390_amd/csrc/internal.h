@@ -51,6 +51,7 @@ struct genie_index {
     int device = 0;
     int scan_threads = kScanThreadsDefault;   // launch shape of the scan kernel
     int scan_unroll = kScanUnrollDefault;
+    int scan_persistent = 0;                  // 1: persistent workgroups over a pair queue
 };
 
 namespace genie {

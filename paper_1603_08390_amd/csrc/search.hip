@@ -42,6 +42,7 @@ struct ScanParams {
     float gate_delta;       // safety margin subtracted from the prediction
     const uint32_t *qlist;  // query of each row (fallback pass) or null
     const uint32_t *qcount; // rows in qlist (device) or null
+    uint32_t *work;         // persistent schedule: 8 per-XCD pair counters (zeroed), or null
 };
 
 struct MergeParams {
@@ -200,10 +201,12 @@ constexpr int scan_waves_per_eu() {
     return (NT == 1024 && (BITS << LG) <= (8 << 16)) ? 8 : 1;
 }
 
+// One (query, tile) pair: the whole of Algorithm 1 over the tile's part of
+// the query's lists, then the tile's exact top-k.  `bc` is the workgroup's
+// static counter array; `smem` the dynamic LDS block.
 template <int BITS, int NT, int U, bool DUMP, int LG>
-__global__ __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<BITS, NT, LG>())))
-void scan_cpq_kernel(ScanParams p) {
+__device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, uint32_t *bc,
+                                          uint32_t *smem) {
     static_assert(BITS == 4 || BITS == 8 || BITS == 16, "power-of-two counter width");
     constexpr uint32_t CPW = 32 / BITS;                   // counters per word
     constexpr uint32_t LCPW = BITS == 4 ? 3 : (BITS == 8 ? 2 : 1);   // log2(CPW)
@@ -215,10 +218,6 @@ void scan_cpq_kernel(ScanParams p) {
     constexpr uint32_t NWAVE = NT / 64;
     constexpr uint32_t CH = 64 * U;                       // dwords per wave per step
 
-    // The Bitmap Counter has a fixed size per counter width; as a static
-    // array at LDS offset 0 its addresses need no base register.
-    __shared__ uint32_t bc[NW];
-    extern __shared__ uint32_t smem[];
     uint32_t *misc = smem;
     const uint32_t lg = p.ht_log2, cap = 1u << lg;
     uint32_t *ht = smem + 32;
@@ -230,14 +229,6 @@ void scan_cpq_kernel(ScanParams p) {
     // per-wave queue of (count << 16 | local id) pairs that passed the gate
     uint32_t *gq = sp_cum + p.max_items + 1 + ((threadIdx.x >> 6) * kGateQueue);
 
-    // XCD-aware mapping: consecutive workgroup ids go to different XCDs, so
-    // give each XCD a contiguous range of (tile, query) pairs, tile-major,
-    // and its L2 keeps serving the same tile's postings.
-    const uint32_t bid = blockIdx.x;
-    const uint64_t pair = (uint64_t)(bid & 7) * p.per_xcd + (bid >> 3);
-    const uint64_t npairs = (uint64_t)p.nq * p.n_tiles;
-    if (pair >= npairs)
-        return;
     const uint32_t t = (uint32_t)(pair / p.nq);
     const uint32_t qrow = (uint32_t)(pair % p.nq);
     if (p.qcount && qrow >= *p.qcount)
@@ -562,6 +553,52 @@ void scan_cpq_kernel(ScanParams p) {
         p.tile_kth[row] = thr;
 }
 
+template <int BITS, int NT, int U, bool DUMP, int LG, bool PERSIST>
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<BITS, NT, LG>())))
+void scan_cpq_kernel(ScanParams p) {
+    constexpr uint32_t CPW = 32 / BITS;
+    constexpr uint32_t NW = (1u << LG) / CPW;
+    // The Bitmap Counter has a fixed size per counter width; as a static
+    // array at LDS offset 0 its addresses need no base register.
+    __shared__ uint32_t bc[NW];
+    extern __shared__ uint32_t smem[];
+    // XCD-aware mapping: consecutive workgroup ids go to different XCDs, so
+    // each XCD gets a contiguous slice of the (tile, query) pairs, tile-major,
+    // and its L2 keeps serving the same tile's postings.
+    const uint32_t bid = blockIdx.x;
+    const uint64_t npairs = (uint64_t)p.nq * p.n_tiles;
+    if constexpr (!PERSIST) {   // one workgroup per pair
+        const uint64_t pair = (uint64_t)(bid & 7) * p.per_xcd + (bid >> 3);
+        if (pair < npairs)
+            scan_pair<BITS, NT, U, DUMP, LG>(p, pair, bc, smem);
+    } else {
+        // Persistent schedule: as many workgroups as fit the device at once,
+        // each taking the next pair of its XCD's slice from that slice's
+        // counter (one atomic per pair), then helping the other slices in
+        // turn.  Every workgroup leaves once all eight counters have run
+        // past their slices.
+        __shared__ uint32_t s_next;
+        uint32_t x = bid & 7;
+        for (uint32_t spent = 0; spent < 8;) {
+            if (threadIdx.x == 0)
+                s_next = atomicAdd(&p.work[x], 1u);
+            __syncthreads();
+            const uint64_t idx = s_next;
+            __syncthreads();
+            const uint64_t first = (uint64_t)x * p.per_xcd;
+            const uint64_t slice = first >= npairs ? 0 : min<uint64_t>(p.per_xcd, npairs - first);
+            if (idx >= slice) {
+                x = (x + 1) & 7;
+                spent++;
+                continue;
+            }
+            scan_pair<BITS, NT, U, DUMP, LG>(p, first + idx, bc, smem);
+            __syncthreads();   // the next pair reuses the LDS
+        }
+    }
+}
+
 // Per query: keep candidates whose count reaches the largest tile k-th count
 // (the global k-th count is at least that), sort them by key, emit top k.
 constexpr int kMergeBuf = 4096;   // keys held in LDS
@@ -647,18 +684,39 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
     }
 }
 
+// Status block: flags, statistics, the fallback count and the persistent
+// schedule's pair counters (words 16..23 for the scan, 24..31 for the
+// fallback pass).
+constexpr uint32_t kStatusWords = 32;
+constexpr uint32_t kWorkWord = 16, kFallbackWorkWord = 24;
 __global__ void clear_status_kernel(uint32_t *status) {
-    if (threadIdx.x < 16)
+    if (threadIdx.x < kStatusWords)
         status[threadIdx.x] = 0;
 }
 
 template <int BITS, int NT, int U, int LG>
 int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipStream_t st) {
-    auto kern = dump ? scan_cpq_kernel<BITS, NT, U, true, LG> : scan_cpq_kernel<BITS, NT, U, false, LG>;
-    GENIE_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds));
+    // the count dump (match-count entry point) always runs 1024 x 4, one
+    // workgroup per pair
+    const void *kern = dump ? (const void *)scan_cpq_kernel<BITS, 1024, 4, true, LG, false>
+                     : sp.work ? (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, true>
+                               : (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, false>;
+    const int nt = dump ? 1024 : NT;
+    GENIE_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (sp.work && !dump) {
+        // persistent schedule: the workgroups that fit the device at once
+        // (a multiple of 8, so that every XCD has the same number)
+        int dev = 0, cus = 0, per_cu = 0;
+        GENIE_HIP(hipGetDevice(&dev));
+        GENIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        GENIE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds));
+        const uint64_t resident = std::max<uint64_t>(8, (uint64_t)cus * std::max(per_cu, 1) / 8 * 8);
+        grid = std::min<uint64_t>(grid, resident);
+    }
+    ScanParams arg = sp;
+    void *args[] = {&arg};
     void *ev = timing_begin(st);
-    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(NT), lds, st, sp);
+    GENIE_HIP(hipLaunchKernel(kern, dim3((uint32_t)grid), dim3(nt), args, lds, st));
     timing_end(ev, st, 0);
     GENIE_HIP(hipGetLastError());
     return GENIE_OK;
@@ -710,7 +768,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
         return GENIE_EINVAL;
     }
     SearchShape shape;
-    int rc = search_shape(max_items, k, ix->scan_threads, ix->tile_log2, &shape);
+    const int threads = dump ? 1024 : ix->scan_threads;   // the count dump runs 1024 x 4
+    int rc = search_shape(max_items, k, threads, ix->tile_log2, &shape);
     if (rc)
         return rc;
     char *ws = static_cast<char *>(d_workspace);
@@ -739,6 +798,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.status = reinterpret_cast<uint32_t *>(ws + L.status);
     sp.gate = d_gate;
     sp.gate_delta = gate_delta;
+    sp.work = (ix->scan_persistent && !dump) ? sp.status + kWorkWord : nullptr;
     const uint64_t grid = sp.per_xcd * 8;
     if (grid > 0x7FFFFFFFull) {
         set_error("too many (query, tile) pairs in one call");
@@ -776,6 +836,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     fp.gate = nullptr;
     fp.qlist = fb_list;
     fp.qcount = fb_count;
+    fp.work = ix->scan_persistent ? sp.status + kFallbackWorkWord : nullptr;
     rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, ix->tile_log2, fp, false,
                        shape.lds_bytes, grid, stream);
     if (rc)

@@ -120,6 +120,39 @@ def test_smaller_tiles(case):
         _check(same, 4, q2, 1000, tile_log2=15)
 
 
+# Persistent workgroups over the pair queue: the same answers for the plain
+# search (several tiles, ragged), every query falling back in the gated
+# search (a second persistent pass), and the count dump.
+@pytest.mark.parametrize("tile_log2", [16, 15])
+def test_persistent_schedule(tile_log2):
+    print("persistent schedule, tile_log2", tile_log2, flush=True)
+    inst = workloads.relational(n=3 * 65535 + 4321, d=20, V=40, nq=70, k=50)
+    oidx = oracle.build_csr(inst.values, inst.V)
+    o_ids, o_cts, kth, _ = oracle.search_idx(oidx, inst.queries, 50)
+    for nt, u in ((1024, 4), (512, 8)):
+        ix = genie.Index(inst.values, inst.V, tile_log2)
+        genie.genie_index_set_scan_shape(ix, nt, u)
+        genie.genie_index_set_scan_schedule(ix, 1)
+        assert ix.info.scan_persistent == 1
+        _check(inst.values, inst.V, inst.queries, 50, ix=ix)
+        off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
+        high = torch.full((inst.queries.n_queries,), 1e9, dtype=torch.float32, device="cuda")
+        g_ids, g_cts, ws = genie.genie_search_gated_async(ix, off, items, 50,
+                                                          inst.queries.max_items(), high, 0.0)
+        torch.cuda.synchronize()
+        st = genie.workspace_stats(ws)
+        assert st["status"] == 0 and st["fallback_queries"] == inst.queries.n_queries
+        assert np.array_equal(genie.as_uint32(g_ids), o_ids)
+        assert np.array_equal(genie.as_uint32(g_cts), o_cts)
+        counts, _ = genie.genie_match_count_async(ix, off, items, inst.queries.max_items())
+        torch.cuda.synchronize()
+        got = genie.as_uint32(counts)
+        for q in (0, 33, 69):
+            want, _ = oracle.match_counts(oidx, inst.queries.items_of(q))
+            assert np.array_equal(got[q], want), q
+        ix.free()
+
+
 @pytest.mark.parametrize("tile_log2", [16, 15])
 def test_match_count_dump_equals_oracle(tile_log2):
     inst = workloads.relational(n=2 * 65536 + 77, d=12, V=48, nq=6)

@@ -21,8 +21,12 @@ def test_autotune_shapes_agree_and_best_is_set(tmp_path):
     cache = str(tmp_path / "tune.json")
     res = autotune.autotune(ix, off, items, 100, inst.queries.max_items(), reps=3,
                             cache_path=cache, key="relational-small")
-    assert set(res["ms"]) == {f"{a}x{b}" for a, b in genie.SCAN_SHAPES}
-    assert res["ms"][f'{res["threads"]}x{res["unroll"]}'] == min(res["ms"].values())
+    assert set(res["ms"]) == {f"{a}x{b}" + ("p" if sch else "") for sch in genie.SCAN_SCHEDULES
+                              for a, b in genie.SCAN_SHAPES}
+    best = f'{res["threads"]}x{res["unroll"]}' + ("p" if res["persistent"] else "")
+    assert res["ms"][best] == min(res["ms"].values())
+    assert ix.info.scan_shape == (res["threads"], res["unroll"])
+    assert ix.info.scan_persistent == res["persistent"]
     again = autotune.autotune(ix, off, items, 100, inst.queries.max_items(), cache_path=cache,
                               key="relational-small")
     assert again["cached"] and again["threads"] == res["threads"]
@@ -43,6 +47,7 @@ def test_autotune_index_picks_a_tiling(tmp_path):
     assert set(rep["ms"]) == {"16", "15"}
     assert ix.info.tile_objects == (1 << rep["tile_log2"]) - 1
     assert ix.info.scan_shape == (rep["threads"], rep["unroll"])
+    assert ix.info.scan_persistent == rep["persistent"]
     off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
     ids, cts, _ = genie.genie_search_async(ix, off, items, 50, inst.queries.max_items())
     o_ids, o_cts, _, _ = oracle.search_idx(oracle.build_csr(inst.values, inst.V),
