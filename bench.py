@@ -2,7 +2,10 @@
 
 A step is one pass of the whole search path over one batch of queries, with
 the index, the queries, the outputs and the workspace already resident in
-HBM.  Two paths are timed, K steps each, on the same batch: the plain c-PQ
+HBM.  Each path first runs K eager steps, with the library's HIP event
+pairs around its own kernel launches (the kernel durations of the roofline),
+then its step is recorded once in a HIP graph and K replays are timed (the
+throughput); every replay's answers equal the eager ones.  Two paths are timed, K steps each, on the same batch: the plain c-PQ
 (AuditThreshold from 1), and the learned gate (query features + MLP
 prediction + gated search with its exact fallback), trained beforehand on a
 separate query set over the same objects; their answers must be identical.
@@ -73,6 +76,11 @@ LDS_ATOMIC_PEAK = 8.34e12
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1603_08390_amd", "csrc", "search.hip")
 
 
+def log(*a):
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def pmc_summary_path(workload: str) -> str:
     return os.path.join(ROOT, "profiles", f"scan_cpq_{workload}_pmc.json")
 
@@ -103,6 +111,7 @@ def cpu_baseline(values, V, queries, k, budget_s: float, chunk: int = 64):
     the batch, wrapping around, until the budget is spent."""
     import threading
     import oracle
+    log("cpu baseline")
     idx = oracle.build_csr(values, V)
     nq = queries.n_queries
 
@@ -154,6 +163,7 @@ def train_gate(genie, torch, ix, sets, epochs: int):
     tx = torch.cat(xs).contiguous()
     ty = torch.cat(ys).contiguous()
     model = gate_mod.GateModel(seed=1)
+    log("training the gate on", tx.shape[0], "queries")
     model.train(tx, ty, epochs=epochs, batch=256, lr=2e-3, tau=0.1)
     model.calibrate(model.predict(tx).cpu().numpy(), ty.cpu().numpy(), target=0.01)
     return model
@@ -189,18 +199,37 @@ class SearchBench:
         self.gws = self.genie.alloc_workspace(gix, self.nq, self.k)
 
     def plain_step(self):
-        off, items = self.prep(self.stream)
+        st = self.torch.cuda.current_stream()
+        off, items = self.prep(st)
         self.genie.genie_search_async(self.ix, off, items, self.k, self.max_items, self.ids,
-                                      self.cts, self.ws, self.stream)
+                                      self.cts, self.ws, st)
 
     def gated_step(self):
         g, m = self.genie, self.model
-        off, items = self.prep(self.stream)
-        g.genie_gate_features_async(self.gix, off, items, self.k, out=self.feats,
-                                    stream=self.stream)
-        m.predict(self.feats, out=self.pred, stream=self.stream)
+        st = self.torch.cuda.current_stream()
+        off, items = self.prep(st)
+        g.genie_gate_features_async(self.gix, off, items, self.k, out=self.feats, stream=st)
+        m.predict(self.feats, out=self.pred, stream=st)
         g.genie_search_gated_async(self.gix, off, items, self.k, self.max_items, self.pred,
-                                   m.delta, self.gids, self.gcts, self.gws, self.stream)
+                                   m.delta, self.gids, self.gcts, self.gws, st)
+
+    def graphed(self, step):
+        """Record one step in a HIP graph (after an eager run on the capture
+        stream) and return its replay.  The library records kernels only
+        (its status clear is a kernel, not a memset)."""
+        torch = self.torch
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            step()
+        torch.cuda.synchronize()
+        self._graphs = getattr(self, "_graphs", []) + [graph]
+        return graph.replay
 
     def timed(self, step, steps, warmup):
         """Warmup steps, then exactly `steps` steps between two device
@@ -216,32 +245,61 @@ class SearchBench:
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    def run(self, steps, warmup, s_total):
-        g = self.genie
+    def run(self, steps, warmup, s_total, graph=False):
+        """Each path: K eager steps with the library's kernel event pairs
+        (the kernel durations), then, with graph=True, K replays of the step
+        recorded in a HIP graph (the throughput); the replays must give the
+        eager answers."""
+        g, torch = self.genie, self.torch
         if self.plain_shape:
             g.genie_index_set_scan_shape(self.ix, *self.plain_shape[:2])
             g.genie_index_set_scan_schedule(self.ix, self.plain_shape[2])
         g.genie_kernel_timing_enable(True)
         g.genie_kernel_timing_read(reset=True)
-        el_plain = self.timed(self.plain_step, steps, warmup)
+        el_plain = eager_plain = self.timed(self.plain_step, steps, warmup)
         kt = g.genie_kernel_timing_read(reset=True)
+        log("plain path, eager:", round(eager_plain * 1e3 / steps, 3), "ms per step")
+        g.genie_kernel_timing_enable(False)
         stats = g.workspace_stats(self.ws)
         if stats["status"] != 0:
             raise RuntimeError(f"device status {stats}")
-        el_gate, gstats, gkt = None, None, None
+        ref = (self.ids.clone(), self.cts.clone())
+        if graph:
+            replay = self.graphed(self.plain_step)
+            self.ids.zero_()
+            replay()
+            torch.cuda.synchronize()
+            if not (torch.equal(self.ids, ref[0]) and torch.equal(self.cts, ref[1])):
+                raise RuntimeError("first graph replay and eager answers differ")
+            el_plain = self.timed(replay, steps, warmup)
+            if not (torch.equal(self.ids, ref[0]) and torch.equal(self.cts, ref[1])):
+                raise RuntimeError("graph replay and eager answers differ")
+        el_gate, gstats, gkt, eager_gate = None, None, None, None
         if self.model is not None:
             if self.gate_shape:
                 g.genie_index_set_scan_shape(self.gix, *self.gate_shape[:2])
                 g.genie_index_set_scan_schedule(self.gix, self.gate_shape[2])
-            el_gate = self.timed(self.gated_step, steps, warmup)
+            g.genie_kernel_timing_enable(True)
+            g.genie_kernel_timing_read(reset=True)
+            el_gate = eager_gate = self.timed(self.gated_step, steps, warmup)
             gkt = g.genie_kernel_timing_read(reset=True)
+            log("gated path, eager:", round(eager_gate * 1e3 / steps, 3), "ms per step")
+            g.genie_kernel_timing_enable(False)
             gstats = g.workspace_stats(self.gws)
             if gstats["status"] != 0:
                 raise RuntimeError(f"device status {gstats}")
-            if not (self.torch.equal(self.gids, self.ids) and
-                    self.torch.equal(self.gcts, self.cts)):
+            if not (torch.equal(self.gids, ref[0]) and torch.equal(self.gcts, ref[1])):
                 raise RuntimeError("gated and plain answers differ")
-        g.genie_kernel_timing_enable(False)
+            if graph:
+                replay = self.graphed(self.gated_step)
+                self.gids.zero_()
+                replay()
+                torch.cuda.synchronize()
+                if not (torch.equal(self.gids, ref[0]) and torch.equal(self.gcts, ref[1])):
+                    raise RuntimeError("first gated graph replay and plain answers differ")
+                el_gate = self.timed(replay, steps, warmup)
+                if not (torch.equal(self.gids, ref[0]) and torch.equal(self.gcts, ref[1])):
+                    raise RuntimeError("gated graph replay and plain answers differ")
 
         nq, k = self.nq, self.k
         scan_ms = kt["scan_ms"] / max(1, kt["scan_launches"])
@@ -265,6 +323,7 @@ class SearchBench:
                        "frac": round(rate / LDS_ATOMIC_PEAK, 4), "postings_per_step": scanned}
         plain = {"value": round(nq * steps / el_plain, 1),
                  "ms_per_step": round(el_plain * 1e3 / steps, 4),
+                 "eager_ms_per_step": round(eager_plain * 1e3 / steps, 4),
                  "gate_passes_per_step": stats["gate_passes"],
                  "ht_inserts_per_step": stats["ht_inserts"],
                  "ht_overflow_tiles": stats["ht_overflow_tiles"],
@@ -275,6 +334,7 @@ class SearchBench:
         if el_gate is not None:
             learned = {"value": round(nq * steps / el_gate, 1),
                        "ms_per_step": round(el_gate * 1e3 / steps, 4),
+                       "eager_ms_per_step": round(eager_gate * 1e3 / steps, 4),
                        "speedup_vs_plain": round(el_plain / el_gate, 4),
                        "identical_results": True,
                        "gate_passes_per_step": gstats["gate_passes"],
@@ -287,8 +347,14 @@ class SearchBench:
         return {"value": round(nq * steps / elapsed, 1),
                 "ms_per_step": round(elapsed * 1e3 / steps, 4),
                 "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
+                "launch": "HIP graph replay" if graph else "eager",
                 "roofline": roofline, "atomic_roof": atomic_roof,
                 "plain_cpq": plain, "learned_gate": learned}
+
+
+def use_graph(args, workload):
+    """HIP graph replay of the step (--graph on|off; auto: on)."""
+    return args.graph in ("auto", "on")
 
 
 def line(args, workload, res, config, dtype="u32"):
@@ -296,7 +362,8 @@ def line(args, workload, res, config, dtype="u32"):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-           "config": dict(config, path=res["path"], parallelism="single GPU")}
+           "config": dict(config, path=res["path"], launch=res["launch"],
+                          parallelism="single GPU")}
     for key in ("roofline", "atomic_roof", "plain_cpq", "learned_gate"):
         out[key] = res[key]
     out["roofline"]["traffic"] = measured_traffic(workload)
@@ -309,8 +376,16 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
     range items, all resident; `train_queries(rng)` draws the gate's
     training set over the same objects."""
     nq, k = inst.queries.n_queries, inst.k
+    log(name, "generated:", inst.n, "objects,", nq, "queries")
     tune, indexes = None, {}
-    if tune_sample:
+    if args.fixed:
+        # a given tiling / shape / schedule for every path, no autotuning
+        lg, nt, u, sched = args.fixed
+        ix = genie.Index(inst.values, inst.V, lg)
+        genie.genie_index_set_scan_shape(ix, nt, u)
+        genie.genie_index_set_scan_schedule(ix, sched)
+        tune_sample = 0
+    elif tune_sample:
         # tiling and scan shape chosen by the autotuner on the batch's first
         # queries, for each path separately (index builds and tuning are
         # outside the timed regions)
@@ -322,6 +397,7 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
         ix = indexes[tune["plain"]["tile_log2"]]
     else:
         ix = genie.Index(inst.values, inst.V)
+    log("index ready:", ix.info)
     off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
     sb = SearchBench(genie, torch, ix, nq, k, inst.queries.max_items(), lambda st: (off, items))
     if tune:
@@ -342,7 +418,8 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
     for lg, other in indexes.items():
         if other is not sb.ix and other is not sb.gix:
             other.free()
-    res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]))
+    res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]),
+                 graph=use_graph(args, name))
     cfg = {"workload": describe, "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V,
            "n_queries": nq, "k": k}
     out = line(args, name, res, cfg)
@@ -438,8 +515,10 @@ def ann_quality(torch, P, Q, found, k):
 
 def bench_ann(args, torch, genie, workloads):
     inp = workloads.ann()
+    log("ann generated")
     lsh = lsh_device(torch, inp)
     ix, sig_h = ann_index(torch, genie, inp, lsh)
+    log("ann index ready:", ix.info)
     nq, m, k = inp.queries.shape[0], inp.a.shape[0], inp.k
     qpts = torch.from_numpy(inp.queries).cuda()
     qsig = torch.empty((nq, m), dtype=torch.int32, device="cuda")
@@ -460,7 +539,7 @@ def bench_ann(args, torch, genie, workloads):
                                           lsh["w"], lsh["rehash"], lsh["log2_buckets"])
         toff, titems = genie.genie_lsh_items_async(tsig)
         sb.model = train_gate(genie, torch, ix, [(toff, titems, m, k)], args.gate_epochs)
-    res = sb.run(args.steps, args.warmup, nq * m)
+    res = sb.run(args.steps, args.warmup, nq * m, graph=use_graph(args, "ann"))
     P = torch.from_numpy(inp.points).cuda()
     rec, ratio = ann_quality(torch, P, qpts, sb.ids, k)
     out = line(args, "ann", res, {
@@ -642,8 +721,15 @@ def main():
                     help="seconds of oracle time for the CPU baseline (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true", help="skip the learned-gate path")
+    ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
+                    help="time HIP graph replays of the step (auto: on); kernel durations "
+                         "always come from an eager pass of the same steps")
     ap.add_argument("--gate-train-queries", type=int, default=4096)
     ap.add_argument("--gate-epochs", type=int, default=30)
+    ap.add_argument("--fixed", default=None, metavar="L,T,U,P",
+                    help="item workloads: tiles of 2^L-1 objects, T threads x U dwords, "
+                         "schedule P (0 grid, 1 persistent) for every path instead of the "
+                         "default or autotuned configuration (e.g. for profiler runs)")
     ap.add_argument("--requests", type=int, default=50000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: execution slots")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: requests per group")
@@ -657,6 +743,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.fixed:
+        args.fixed = tuple(int(x) for x in args.fixed.split(","))
+        if len(args.fixed) != 4:
+            ap.error("--fixed takes L,T,U,P")
     heavy = args.workload == "uneven"
     if args.steps is None:
         args.steps = 3 if heavy else 50

@@ -93,3 +93,13 @@ def test_oracle_shares_no_code_with_library():
     for f in os.listdir(csrc):
         assert "oracle" not in open(os.path.join(csrc, f)).read().lower(), f
     assert "oracle" not in open(os.path.join(ROOT, "paper_1603_08390_amd", "__init__.py")).read()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
