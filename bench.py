@@ -643,9 +643,17 @@ def bench_serving(args, torch, genie, workloads):
                                            point=inp.queries[q]))
         return out
 
-    def run(arrivals, use_gate):
+    executors = {}
+
+    def run(arrivals, use_gate, graphs=None):
         import gc
-        srv = serving.Server(res, slots=args.slots, max_batch=args.max_batch, use_gate=use_gate)
+        graphs = args.serving_graphs if graphs is None else graphs
+        key = (use_gate, graphs)
+        if key not in executors:   # graphs are recorded once per executor
+            executors[key] = (serving.GraphExecutor(res, args.slots, args.max_batch, use_gate)
+                              if graphs else serving.GpuExecutor(res, args.slots, use_gate))
+        srv = serving.Server(res, slots=args.slots, max_batch=args.max_batch,
+                             executor=executors[key])
         batch = requests(arrivals)
         gc.collect()
         gc.disable()
@@ -686,6 +694,19 @@ def bench_serving(args, torch, genie, workloads):
                       "learned_gate": pg})
     head = min(sweep, key=lambda r: abs(r["load"] - 0.7))
     rate, pois_plain, pois_gate = head["offered_qps"], head["plain"], head["learned_gate"]
+    # the other executor at saturation and at the headline load, same arrivals
+    other = not args.serving_graphs
+    arr = serving.poisson_arrivals(
+        np.random.default_rng(workloads.BASE_SEED + 108 + sweep.index(head)), n_req,
+        head["offered_qps"])
+    run(zero, False, other)
+    compare = {"executor": "graph" if other else "eager",
+               "saturated_plain": run(zero, False, other)[1],
+               "poisson_plain": run(arr, False, other)[1]}
+    if not args.no_gate:
+        run(zero, True, other)
+        compare["saturated_gate"] = run(zero, True, other)[1]
+        compare["poisson_gate"] = run(arr, True, other)[1]
     best = pois_gate if pois_gate and pois_gate["qps"] > pois_plain["qps"] else pois_plain
     ms = n_req / best["qps"] * 1e3 if best["qps"] > 0 else 0.0   # the whole request stream
     out = {"metric": METRICS["serving"], "value": best["qps"], "unit": "queries/s",
@@ -702,6 +723,8 @@ def bench_serving(args, torch, genie, workloads):
                          "identical_results": sat_gate is not None},
            "poisson": {"plain": pois_plain, "learned_gate": pois_gate},
            "load_sweep": sweep,
+           "executor": "graph" if args.serving_graphs else "eager",
+           "other_executor": compare,
            "groups": groups,
            "cpu_baseline": None}
     rel_ix.free()
@@ -733,6 +756,8 @@ def main():
     ap.add_argument("--requests", type=int, default=50000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: execution slots")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: requests per group")
+    ap.add_argument("--serving-executor", choices=("graph", "eager"), default="graph",
+                    help="serving: replay per-(slot, index, k) HIP graphs, or launch eagerly")
     ap.add_argument("--loads", default="0.3,0.5,0.7,0.9",
                     help="serving: offered loads as fractions of the saturated plain rate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -743,6 +768,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    args.serving_graphs = args.serving_executor == "graph"
     if args.fixed:
         args.fixed = tuple(int(x) for x in args.fixed.split(","))
         if len(args.fixed) != 4:

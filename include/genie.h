@@ -217,6 +217,26 @@ int genie_search_gated_async(const genie_index *ix, const uint64_t *d_q_offsets,
                              void *d_workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * genie_search_async (d_gate NULL) or genie_search_gated_async (d_gate set)
+ * over the first *d_rows of a batch laid out for `capacity` queries, the
+ * count read on the device when the kernels run.  For callers that record
+ * the launches once in a HIP graph and replay them on batches of any size
+ * up to the capacity (the buffers and the workspace are sized for it): rows
+ * at or past *d_rows are neither scanned nor written.
+ *   d_q_offsets: device, capacity + 1 uint64 (entries past the live rows
+ *                are not read by the search); d_gate: capacity float32.
+ *   d_rows: device, one uint32 <= capacity.
+ *   Other arguments, the workspace and errors as genie_search_async with
+ *   n_queries = capacity.
+ */
+int genie_search_rows_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                            const genie_item *d_items, uint64_t n_items, uint32_t capacity,
+                            const uint32_t *d_rows, uint32_t max_items, uint32_t k,
+                            const float *d_gate, float gate_delta, uint32_t *d_out_ids,
+                            uint32_t *d_out_counts, void *d_workspace, size_t workspace_bytes,
+                            void *stream);
+
+/*
  * Queries of the LSH transform (Section 4.1.1): query q is the items
  * (i, sig[q][i], sig[q][i]) for i = 0..m-1, i.e. one exact keyword per hash
  * function.

@@ -41,7 +41,7 @@ EXPORTED = (
     "genie_kernel_timing_read", "genie_search_gated_async", "genie_gate_features_async",
     "genie_gate_forward_async", "genie_gate_workspace_size", "genie_gate_backward_async",
     "genie_gate_adam_async", "genie_lsh_items_async", "genie_index_set_scan_shape",
-    "genie_index_set_scan_schedule",
+    "genie_index_set_scan_schedule", "genie_search_rows_async",
 )
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
@@ -106,6 +106,9 @@ def load() -> ctypes.CDLL:
     lib.genie_search_gated_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, f32, vp, vp, vp,
                                              sz, vp]
     lib.genie_search_gated_async.restype = ctypes.c_int
+    lib.genie_search_rows_async.argtypes = [vp, vp, vp, u64, u32, vp, u32, u32, vp, f32, vp, vp,
+                                            vp, sz, vp]
+    lib.genie_search_rows_async.restype = ctypes.c_int
     lib.genie_gate_features_async.argtypes = [vp, vp, vp, u64, u32, u32, vp, vp]
     lib.genie_gate_features_async.restype = ctypes.c_int
     lib.genie_gate_forward_async.argtypes = [vp, vp, vp, u32, vp, vp]
@@ -301,6 +304,26 @@ def genie_search_gated_async(index: Index, d_q_offsets, d_items, k: int, max_ite
                                            _dev_ptr(out_counts), _dev_ptr(workspace),
                                            workspace.numel(), _stream_handle(stream)))
     return out_ids, out_counts, workspace
+
+
+def genie_search_rows_async(index: Index, d_q_offsets, d_items, d_rows, k: int, max_items: int,
+                            out_ids, out_counts, workspace, d_gate=None, gate_delta: float = 0.0,
+                            stream=None):
+    """Search (gated when d_gate is given) over the first d_rows[0] queries of
+    a batch laid out for capacity = d_q_offsets.numel() - 1 queries; the row
+    count is read on the device, so a HIP graph recorded once serves any
+    batch size up to the capacity."""
+    capacity = d_q_offsets.numel() - 1
+    if d_rows.numel() != 1 or out_ids.shape[0] < capacity or out_counts.shape[0] < capacity:
+        raise ValueError("buffers do not fit the capacity")
+    _check(load().genie_search_rows_async(index.handle, _dev_ptr(d_q_offsets), _dev_ptr(d_items),
+                                          d_items.numel() // 3, capacity, _dev_ptr(d_rows),
+                                          int(max_items), int(k),
+                                          _dev_ptr(d_gate) if d_gate is not None else None,
+                                          float(gate_delta), _dev_ptr(out_ids),
+                                          _dev_ptr(out_counts), _dev_ptr(workspace),
+                                          workspace.numel(), _stream_handle(stream)))
+    return out_ids, out_counts
 
 
 def genie_gate_features_async(index: Index, d_q_offsets, d_items, k: int, out=None, stream=None):

@@ -337,12 +337,10 @@ static int check_common(const genie_index *ix, uint32_t n_queries, uint32_t k) {
     return GENIE_OK;
 }
 
-extern "C" int genie_search_async(const genie_index *ix, const uint64_t *d_q_offsets,
-                                  const genie_item *d_items, uint64_t n_items,
-                                  uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
-                                  uint32_t *d_out_counts, void *d_workspace,
-                                  size_t workspace_bytes, void *stream) {
-    clear_error();
+namespace {
+int check_async(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
+                uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                uint32_t *d_out_counts, void *d_workspace) {
     int rc = check_common(ix, n_queries, k);
     if (rc)
         return rc;
@@ -360,6 +358,32 @@ extern "C" int genie_search_async(const genie_index *ix, const uint64_t *d_q_off
         set_error("workspace must be 256-byte aligned");
         return GENIE_EINVAL;
     }
+    return GENIE_OK;
+}
+
+int check_gate(const float *d_gate, float gate_delta) {
+    if (!d_gate) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (!(gate_delta >= 0.0f)) {
+        set_error("gate_delta must be >= 0");
+        return GENIE_EINVAL;
+    }
+    return GENIE_OK;
+}
+}  // namespace
+
+extern "C" int genie_search_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                                  const genie_item *d_items, uint64_t n_items,
+                                  uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                                  uint32_t *d_out_counts, void *d_workspace,
+                                  size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = check_async(ix, d_q_offsets, d_items, n_queries, max_items, k, d_out_ids,
+                         d_out_counts, d_workspace);
+    if (rc || n_queries == 0)
+        return rc;
     return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, k, d_out_ids,
                          d_out_counts, nullptr, d_workspace, workspace_bytes,
                          (hipStream_t)stream);
@@ -372,30 +396,38 @@ extern "C" int genie_search_gated_async(const genie_index *ix, const uint64_t *d
                                         uint32_t *d_out_ids, uint32_t *d_out_counts,
                                         void *d_workspace, size_t workspace_bytes, void *stream) {
     clear_error();
-    int rc = check_common(ix, n_queries, k);
-    if (rc)
+    int rc = check_async(ix, d_q_offsets, d_items, n_queries, max_items, k, d_out_ids,
+                         d_out_counts, d_workspace);
+    if (rc || n_queries == 0)
         return rc;
-    if (n_queries == 0)
-        return GENIE_OK;
-    if (!d_q_offsets || !d_items || !d_out_ids || !d_out_counts || !d_workspace || !d_gate) {
-        set_error("null pointer");
-        return GENIE_EINVAL;
-    }
-    if (max_items > GENIE_MAX_ITEMS) {
-        set_error("max_items=%u above %u", max_items, GENIE_MAX_ITEMS);
-        return GENIE_ERANGE;
-    }
-    if (((uintptr_t)d_workspace & 255) != 0) {
-        set_error("workspace must be 256-byte aligned");
-        return GENIE_EINVAL;
-    }
-    if (!(gate_delta >= 0.0f)) {
-        set_error("gate_delta must be >= 0");
-        return GENIE_EINVAL;
-    }
+    if ((rc = check_gate(d_gate, gate_delta)))
+        return rc;
     return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, k, d_out_ids,
                          d_out_counts, nullptr, d_workspace, workspace_bytes,
                          (hipStream_t)stream, d_gate, gate_delta);
+}
+
+extern "C" int genie_search_rows_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                                       const genie_item *d_items, uint64_t n_items,
+                                       uint32_t capacity, const uint32_t *d_rows,
+                                       uint32_t max_items, uint32_t k, const float *d_gate,
+                                       float gate_delta, uint32_t *d_out_ids,
+                                       uint32_t *d_out_counts, void *d_workspace,
+                                       size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = check_async(ix, d_q_offsets, d_items, capacity, max_items, k, d_out_ids,
+                         d_out_counts, d_workspace);
+    if (rc || capacity == 0)
+        return rc;
+    if (!d_rows) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (d_gate && (rc = check_gate(d_gate, gate_delta)))
+        return rc;
+    return launch_search(ix, d_q_offsets, d_items, n_items, capacity, max_items, k, d_out_ids,
+                         d_out_counts, nullptr, d_workspace, workspace_bytes,
+                         (hipStream_t)stream, d_gate, gate_delta, d_rows);
 }
 
 extern "C" int genie_match_count_async(const genie_index *ix, const uint64_t *d_q_offsets,

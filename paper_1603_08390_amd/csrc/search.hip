@@ -759,7 +759,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
                   size_t workspace_bytes, hipStream_t stream, const float *d_gate,
-                  float gate_delta) {
+                  float gate_delta, const uint32_t *d_rows) {
     const bool dump = d_full_counts != nullptr;
     const WorkspaceLayout L = workspace_layout(ix, n_queries, k);
     if (workspace_bytes < L.total) {
@@ -799,6 +799,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.gate = d_gate;
     sp.gate_delta = gate_delta;
     sp.work = (ix->scan_persistent && !dump) ? sp.status + kWorkWord : nullptr;
+    sp.qcount = d_rows;   // live rows (device), or null: all n_queries
     const uint64_t grid = sp.per_xcd * 8;
     if (grid > 0x7FFFFFFFull) {
         set_error("too many (query, tile) pairs in one call");
@@ -818,6 +819,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     mp.k = k;
     mp.out_ids = d_out_ids;
     mp.out_counts = d_out_counts;
+    mp.qcount = d_rows;
     uint32_t *fb_count = sp.status + kStatusFallbackWord;
     uint32_t *fb_list = reinterpret_cast<uint32_t *>(ws + L.fb_list);
     if (d_gate) {

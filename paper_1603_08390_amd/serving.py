@@ -30,7 +30,7 @@ import numpy as np
 
 from . import (Index, alloc_workspace, as_uint32, genie_gate_features_async,
                genie_lsh_items_async, genie_lsh_signatures, genie_search_async,
-               genie_search_gated_async, genie_search_workspace_size)
+               genie_search_gated_async, genie_search_rows_async, genie_search_workspace_size)
 
 
 @dataclasses.dataclass
@@ -138,6 +138,119 @@ class GpuExecutor:
         return handle["ids"].numpy().view(np.uint32), handle["cts"].numpy().view(np.uint32)
 
 
+class _Plan:
+    """Device and pinned host buffers of one (slot, index, k) at the group
+    capacity, and the HIP graph of its launches."""
+
+
+class GraphExecutor(GpuExecutor):
+    """Runs groups by replaying HIP graphs: one per (slot, index, k), recorded
+    on first use at the group capacity, with the group's size passed as a
+    device row count (genie_search_rows_async), so one graph serves every
+    group size.  A launch is then the host-to-device copies of the group's
+    inputs, one graph replay and the copy of the answers to pinned host
+    memory, all on the slot's stream.  The graph holds kernels only (the
+    library's status clear is a kernel, no memset node)."""
+
+    def __init__(self, residents: Dict[str, Resident], slots: int, capacity: int,
+                 use_gate: bool = True):
+        super().__init__(residents, slots, use_gate)
+        self.capacity = capacity
+        self.plans = {}
+
+    def _plan(self, slot: int, target: str, k: int) -> _Plan:
+        key = (slot, target, k)
+        if key in self.plans:
+            return self.plans[key]
+        torch, r, cap, dev = self.torch, self.res[target], self.capacity, "cuda"
+        P = _Plan()
+        P.rows = torch.zeros(1, dtype=torch.int32, device=dev)
+        P.h_rows = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        if r.lsh is not None:
+            m = r.lsh["a"].shape[0]
+            dim = r.lsh["a"].shape[1]
+            P.pts = torch.zeros((cap, dim), dtype=torch.float32, device=dev)
+            P.h_pts = torch.zeros((cap, dim), dtype=torch.float32, pin_memory=True)
+            P.sig = torch.zeros((cap, m), dtype=torch.int32, device=dev)
+            P.off = torch.zeros(cap + 1, dtype=torch.int64, device=dev)
+            P.items = torch.zeros((cap * m, 3), dtype=torch.int32, device=dev)
+            P.max_items = m
+        else:
+            P.max_items = max(1, r.max_items)
+            P.off = torch.zeros(cap + 1, dtype=torch.int64, device=dev)
+            P.items = torch.zeros((cap * P.max_items, 3), dtype=torch.int32, device=dev)
+            P.h_off = torch.zeros(cap + 1, dtype=torch.int64, pin_memory=True)
+            P.h_items = torch.zeros((cap * P.max_items, 3), dtype=torch.int32, pin_memory=True)
+        P.ids = torch.empty((cap, k), dtype=torch.int32, device=dev)
+        P.cts = torch.empty((cap, k), dtype=torch.int32, device=dev)
+        P.h_ids = torch.empty((cap, k), dtype=torch.int32, pin_memory=True)
+        P.h_cts = torch.empty((cap, k), dtype=torch.int32, pin_memory=True)
+        P.ws = alloc_workspace(r.index, cap, k, dev)
+        gated = self.use_gate and r.gate is not None
+        if gated:
+            P.feats = torch.zeros((cap, 64), dtype=torch.float32, device=dev)
+            P.pred = torch.zeros(cap, dtype=torch.float32, device=dev)
+
+        def step():
+            st = torch.cuda.current_stream()
+            if r.lsh is not None:
+                genie_lsh_signatures(P.pts, r.lsh["a"], r.lsh["b"], r.lsh["w"], r.lsh["rehash"],
+                                     r.lsh["log2_buckets"], out=P.sig, stream=st)
+                genie_lsh_items_async(P.sig, out=(P.off, P.items), stream=st)
+            if gated:
+                genie_gate_features_async(r.index, P.off, P.items, k, out=P.feats, stream=st)
+                r.gate.predict(P.feats, out=P.pred, stream=st)
+            genie_search_rows_async(r.index, P.off, P.items, P.rows, k, P.max_items, P.ids, P.cts,
+                                    P.ws, d_gate=P.pred if gated else None,
+                                    gate_delta=r.gate.delta if gated else 0.0, stream=st)
+
+        st = self.streams[slot]
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            step()                     # eager run: kernel attributes, allocator
+        st.synchronize()
+        P.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(P.graph, stream=st):
+            step()
+        st.synchronize()
+        P.bytes = (P.ws.numel() + 2 * P.ids.numel() * 4 + P.items.numel() * 4 +
+                   P.off.numel() * 8 + (cap * 64 * 4 if gated else 0))
+        self.plans[key] = P
+        return P
+
+    def launch(self, slot, group):
+        torch = self.torch
+        r = self.res[group[0].target]
+        n, k = len(group), group[0].k
+        if n > self.capacity:
+            raise ValueError("group larger than the graph capacity")
+        P = self._plan(slot, group[0].target, k)
+        st = self.streams[slot]
+        with torch.cuda.stream(st):
+            if r.lsh is not None:
+                P.h_pts[:n].numpy()[:] = np.stack([q.point for q in group])
+                P.pts[:n].copy_(P.h_pts[:n], non_blocking=True)
+            else:
+                lens = [len(q.items) for q in group]
+                o = P.h_off.numpy()
+                o[0] = 0
+                o[1:n + 1] = np.cumsum(lens)
+                o[n + 1:] = o[n]               # rows past the group: empty queries
+                if o[n]:
+                    P.h_items.numpy()[:o[n]] = np.concatenate(
+                        [q.items for q in group]).astype(np.uint32).reshape(-1, 3).view(np.int32)
+                P.off.copy_(P.h_off, non_blocking=True)
+                P.items[:max(1, o[n])].copy_(P.h_items[:max(1, o[n])], non_blocking=True)
+            P.h_rows.numpy()[0] = n
+            P.rows.copy_(P.h_rows, non_blocking=True)
+            P.graph.replay()
+            P.h_ids[:n].copy_(P.ids[:n], non_blocking=True)
+            P.h_cts[:n].copy_(P.cts[:n], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return {"event": ev, "ids": P.h_ids[:n], "cts": P.h_cts[:n], "ws": P.ws}
+
+
 class Server:
     """Continuous batching over `slots` execution slots.  The executor runs
     groups; this class decides when and what: arrival, grouping by (index,
@@ -145,8 +258,11 @@ class Server:
 
     def __init__(self, residents: Optional[Dict[str, Resident]] = None, slots: int = 4,
                  max_batch: int = 256, hbm_budget: Optional[int] = None, use_gate: bool = True,
-                 executor=None):
-        self.ex = executor if executor is not None else GpuExecutor(residents, slots, use_gate)
+                 executor=None, graphs: bool = False):
+        if executor is None:
+            executor = (GraphExecutor(residents, slots, max_batch, use_gate) if graphs else
+                        GpuExecutor(residents, slots, use_gate))
+        self.ex = executor
         self.n_slots = slots
         self.max_batch = max_batch
         self.budget = hbm_budget if hbm_budget is not None else int(self.ex.free_memory() * 0.5)

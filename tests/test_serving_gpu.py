@@ -73,3 +73,34 @@ def test_admission_waits_for_memory():
     assert len(out) == len(reqs)
     assert srv.waited_for_memory > 0
     assert srv.in_use == 0
+
+
+def test_graph_executor_equals_eager():
+    """Groups replayed from HIP graphs recorded at the capacity (any group
+    size through the device row count), with and without a gate model
+    (untrained: its predictions send queries through the fallback), give
+    the eager executor's answers bit for bit, and the oracle's."""
+    from paper_1603_08390_amd import gate as gate_mod
+    rel, inp, res = _residents()
+    g = gate_mod.GateModel(seed=3)
+    g.delta = 0.0
+    res["rel"].gate = g
+    rng = np.random.default_rng(21)
+    reqs = _requests(rel, inp, rng, rate=3000.0)
+    for use_gate in (False, True):
+        eager = {r.rid: r for r in serving.Server(res, slots=2, max_batch=16,
+                                                  use_gate=use_gate).run(reqs)}
+        srv = serving.Server(res, slots=2, max_batch=16, use_gate=use_gate, graphs=True)
+        graphed = {r.rid: r for r in srv.run(reqs)}
+        assert isinstance(srv.ex, serving.GraphExecutor) and srv.ex.plans
+        assert set(eager) == set(graphed) == {r.rid for r in reqs}
+        for rid in eager:
+            assert np.array_equal(eager[rid].ids, graphed[rid].ids), (use_gate, rid)
+            assert np.array_equal(eager[rid].counts, graphed[rid].counts), (use_gate, rid)
+    oidx = oracle.build_csr(rel.values, rel.V)
+    for rq in reqs[:40]:
+        if rq.target == "rel":
+            q = workloads.Queries(np.array([0, len(rq.items)], np.uint64), rq.items)
+            o_ids, o_cts, _, _ = oracle.search_idx(oidx, q, rq.k)
+            assert np.array_equal(graphed[rq.rid].ids, o_ids[0])
+            assert np.array_equal(graphed[rq.rid].counts, o_cts[0])
