@@ -339,43 +339,62 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     uint32_t si = 0, c_lo = 0;
     uint32_t c_hi = s ? __builtin_amdgcn_readfirstlane(sp_cum[1]) : 0u;
     uint32_t dwb = s ? __builtin_amdgcn_readfirstlane(sp_dw[0]) : 0u;
-    for (uint32_t cb = wave * CH; cb < total_dw; cb += NWAVE * CH) {
-        uint32_t off[U];
+    // dword offsets (in the tile) of the U pieces that start at stream
+    // position cb; the cursor only moves forward, and pieces past the end
+    // read the tile's trailing padding dwords
+    uint32_t off[U];
+    auto piece_offsets = [&](uint32_t cb) {
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const uint32_t p0 = cb + u * 64;
-            if (p0 >= total_dw) {
-                off[u] = sent_dw + lane;
-            } else {
-                while (p0 >= c_hi) {   // next run (runs of no dwords are skipped)
-                    si++;
-                    c_lo = c_hi;
-                    c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
-                    dwb = __builtin_amdgcn_readfirstlane(sp_dw[si]);
-                }
-                if (p0 + 64 <= c_hi) {
-                    off[u] = (dwb + (p0 - c_lo)) + lane;   // scalar part + lane
-                } else {   // the piece reaches into later runs or past the end
-                    const uint32_t pos = p0 + lane;
-                    if (pos < total_dw) {
-                        uint32_t li = si, l_lo = c_lo, l_hi = c_hi, l_dwb = dwb;
-                        while (pos >= l_hi) {
-                            li++;
-                            l_lo = l_hi;
-                            l_hi = sp_cum[li + 1];
-                            l_dwb = sp_dw[li];
+            for (int u = 0; u < U; u++) {
+                const uint32_t p0 = cb + u * 64;
+                if (p0 >= total_dw) {
+                    off[u] = sent_dw + lane;
+                } else {
+                    while (p0 >= c_hi) {   // next run (runs of no dwords are skipped)
+                        si++;
+                        c_lo = c_hi;
+                        c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
+                        dwb = __builtin_amdgcn_readfirstlane(sp_dw[si]);
+                    }
+                    if (p0 + 64 <= c_hi) {
+                        off[u] = (dwb + (p0 - c_lo)) + lane;   // scalar part + lane
+                    } else {   // the piece reaches into later runs or past the end
+                        const uint32_t pos = p0 + lane;
+                        if (pos < total_dw) {
+                            uint32_t li = si, l_lo = c_lo, l_hi = c_hi, l_dwb = dwb;
+                            while (pos >= l_hi) {
+                                li++;
+                                l_lo = l_hi;
+                                l_hi = sp_cum[li + 1];
+                                l_dwb = sp_dw[li];
+                            }
+                            off[u] = l_dwb + (pos - l_lo);
+                        } else {
+                            off[u] = sent_dw + lane;
                         }
-                        off[u] = l_dwb + (pos - l_lo);
-                    } else {
-                        off[u] = sent_dw + lane;
                     }
                 }
             }
-        }
+    };
+    // Software pipelining: each step issues the next step's posting loads
+    // before its own counting, so the load latency (from L2, the Infinity
+    // Cache or HBM) overlaps the LDS atomics; the scheduling barrier keeps
+    // the compiler from sinking those loads below the atomics.
+    uint32_t nv[U];
+    piece_offsets(wave * CH);
+#pragma unroll
+    for (int u = 0; u < U; u++)   // uniform 64-bit base + 32-bit byte offset
+        nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + (off[u] << 2));
+    for (uint32_t cb = wave * CH; cb < total_dw; cb += NWAVE * CH) {
         uint32_t v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++)   // uniform 64-bit base + 32-bit byte offset
-            v[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + (off[u] << 2));
+        for (int u = 0; u < U; u++)
+            v[u] = nv[u];
+        piece_offsets(cb + NWAVE * CH);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + (off[u] << 2));
+        __builtin_amdgcn_sched_barrier(0);
         uint32_t at_reg = lds_load(&misc[M_AT]);
         const uint32_t at_m1 = at_reg - 1;   // val = f + 1 >= AT  <=>  f >= AT - 1
         // all increments first (no branch between the LDS atomics, so their
