@@ -72,6 +72,12 @@ def test_argument_errors_without_device():
     # n = 0 is a no-op
     assert lib.genie_lsh_signatures(None, 0, 4, None, None, ctypes.c_float(1.0), 3, None, 13,
                                     None, None) == genie.GENIE_OK
+    # schedule and row-count search on a null index
+    assert lib.genie_index_set_scan_schedule(None, 0) == genie.GENIE_EINVAL
+    assert lib.genie_index_set_scan_shape(None, 1024, 4) == genie.GENIE_EINVAL
+    assert lib.genie_search_rows_async(None, None, None, 0, 4, None, 8, 10, None,
+                                       ctypes.c_float(0.0), None, None, None, 0,
+                                       None) == genie.GENIE_EINVAL
 
 
 def test_header_limits_match_binding():
