@@ -236,6 +236,61 @@ int genie_search_rows_async(const genie_index *ix, const uint64_t *d_q_offsets,
                             uint32_t *d_out_counts, void *d_workspace, size_t workspace_bytes,
                             void *stream);
 
+/* ---- multiple loadings: an index streamed to the device in parts -------- */
+
+typedef struct genie_parts genie_parts; /* opaque, owned by the library */
+
+typedef struct {
+    uint64_t n_objects;
+    uint32_t n_parts;
+    uint32_t tiles_total;      /* tiles over all parts */
+    uint64_t part_objects;
+    uint64_t host_bytes;       /* pinned host memory holding the parts' indexes */
+    uint64_t device_bytes;     /* the two device slots the parts stream through */
+} genie_parts_info;
+
+/*
+ * Multiple loadings (Section 3.4), for an index larger than the device
+ * memory the caller gives it: objects [p * part_objects, (p + 1) *
+ * part_objects) form part p, whose index (the layout of genie_build_index,
+ * tiles of 2^tile_log2 - 1 objects, tile_log2 = 15 or 16) is built once into
+ * pinned host memory.  Two device slots, each sized for the largest part,
+ * are allocated here.  values, n_objects, n_dims, n_buckets as
+ * genie_build_index; part_objects >= 1.
+ * Errors: GENIE_EINVAL, GENIE_ENOMEM, GENIE_EDEVICE.
+ */
+int genie_parts_build(const uint32_t *values, uint64_t n_objects, uint32_t n_dims,
+                      uint32_t n_buckets, uint64_t part_objects, uint32_t tile_log2,
+                      genie_parts **out);
+
+/* Free the parts, their pinned host memory and device slots.  NULL is ignored. */
+void genie_parts_free(genie_parts *parts);
+
+/* Describe a parts index.  Errors: GENIE_EINVAL. */
+int genie_parts_info_get(const genie_parts *parts, genie_parts_info *out);
+
+/* Workspace bytes for genie_parts_search_async (0 for a NULL parts index). */
+size_t genie_parts_workspace_size(const genie_parts *parts, uint32_t n_queries, uint32_t k);
+
+/*
+ * Top-k match-count search over all parts, identical to genie_search_async
+ * on one index of all the objects.  Each part is copied into one of the two
+ * slots on the library's own copy stream while the previous part is
+ * scanned on `stream` (events order the copy into a slot after the last
+ * scan that read it); every part's scan writes its tiles' exact top-k lists
+ * into its own columns of one candidate array, ids offset by the part's
+ * first object, and one merge over all columns on `stream` gives the answer
+ * (Section 3.4's merge of the parts' results, on the device).  Arguments,
+ * layout and errors as genie_search_async; the workspace has
+ * genie_parts_workspace_size bytes.  Calls on one parts index run one at a
+ * time: make them on one stream, or wait for a call before starting another.
+ */
+int genie_parts_search_async(genie_parts *parts, const uint64_t *d_q_offsets,
+                             const genie_item *d_items, uint64_t n_items, uint32_t n_queries,
+                             uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                             uint32_t *d_out_counts, void *d_workspace, size_t workspace_bytes,
+                             void *stream);
+
 /*
  * Queries of the LSH transform (Section 4.1.1): query q is the items
  * (i, sig[q][i], sig[q][i]) for i = 0..m-1, i.e. one exact keyword per hash

@@ -41,7 +41,9 @@ EXPORTED = (
     "genie_kernel_timing_read", "genie_search_gated_async", "genie_gate_features_async",
     "genie_gate_forward_async", "genie_gate_workspace_size", "genie_gate_backward_async",
     "genie_gate_adam_async", "genie_lsh_items_async", "genie_index_set_scan_shape",
-    "genie_index_set_scan_schedule", "genie_search_rows_async",
+    "genie_index_set_scan_schedule", "genie_search_rows_async", "genie_parts_build",
+    "genie_parts_free", "genie_parts_info_get", "genie_parts_workspace_size",
+    "genie_parts_search_async",
 )
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
@@ -56,6 +58,12 @@ class GenieError(RuntimeError):
 class _KernelTimes(ctypes.Structure):
     _fields_ = [("scan_launches", ctypes.c_uint64), ("scan_ms", ctypes.c_double),
                 ("merge_launches", ctypes.c_uint64), ("merge_ms", ctypes.c_double)]
+
+
+class _PartsInfo(ctypes.Structure):
+    _fields_ = [("n_objects", ctypes.c_uint64), ("n_parts", ctypes.c_uint32),
+                ("tiles_total", ctypes.c_uint32), ("part_objects", ctypes.c_uint64),
+                ("host_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64)]
 
 
 class _IndexInfo(ctypes.Structure):
@@ -109,6 +117,16 @@ def load() -> ctypes.CDLL:
     lib.genie_search_rows_async.argtypes = [vp, vp, vp, u64, u32, vp, u32, u32, vp, f32, vp, vp,
                                             vp, sz, vp]
     lib.genie_search_rows_async.restype = ctypes.c_int
+    lib.genie_parts_build.argtypes = [vp, u64, u32, u32, u64, u32, ctypes.POINTER(vp)]
+    lib.genie_parts_build.restype = ctypes.c_int
+    lib.genie_parts_free.argtypes = [vp]
+    lib.genie_parts_free.restype = None
+    lib.genie_parts_info_get.argtypes = [vp, ctypes.POINTER(_PartsInfo)]
+    lib.genie_parts_info_get.restype = ctypes.c_int
+    lib.genie_parts_workspace_size.argtypes = [vp, u32, u32]
+    lib.genie_parts_workspace_size.restype = sz
+    lib.genie_parts_search_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, vp, vp, sz, vp]
+    lib.genie_parts_search_async.restype = ctypes.c_int
     lib.genie_gate_features_async.argtypes = [vp, vp, vp, u64, u32, u32, vp, vp]
     lib.genie_gate_features_async.restype = ctypes.c_int
     lib.genie_gate_forward_async.argtypes = [vp, vp, vp, u32, vp, vp]
@@ -208,6 +226,88 @@ class Index:
             self.free()
         except Exception:
             pass
+
+
+class PartsIndex:
+    """genie_parts_build: multiple loadings (Section 3.4).  The index is cut
+    into parts of `part_objects` objects kept in pinned host memory and
+    streamed through two device slots by every search."""
+
+    def __init__(self, values: np.ndarray, n_buckets: int, part_objects: int,
+                 tile_log2: int = 16):
+        values = np.ascontiguousarray(values, dtype=np.uint32)
+        if values.ndim != 2:
+            raise ValueError("values must be [n_objects, n_dims]")
+        h = ctypes.c_void_p()
+        _check(load().genie_parts_build(_np_ptr(values), values.shape[0], values.shape[1],
+                                        int(n_buckets), int(part_objects), int(tile_log2),
+                                        ctypes.byref(h)))
+        self._h = h
+        info = _PartsInfo()
+        _check(load().genie_parts_info_get(self._h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _PartsInfo._fields_}
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise GenieError(GENIE_EINVAL, "parts index is freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            load().genie_parts_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def workspace(self, n_queries: int, k: int, device="cuda"):
+        import torch
+        nbytes = load().genie_parts_workspace_size(self.handle, int(n_queries), int(k))
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def genie_parts_build(values: np.ndarray, n_buckets: int, part_objects: int,
+                      tile_log2: int = 16) -> PartsIndex:
+    return PartsIndex(values, n_buckets, part_objects, tile_log2)
+
+
+def genie_parts_free(parts: PartsIndex):
+    parts.free()
+
+
+def genie_parts_info_get(parts: PartsIndex) -> dict:
+    return dict(parts.info)
+
+
+def genie_parts_workspace_size(parts: PartsIndex, n_queries: int, k: int) -> int:
+    return int(load().genie_parts_workspace_size(parts.handle, int(n_queries), int(k)))
+
+
+def genie_parts_search_async(parts: PartsIndex, d_q_offsets, d_items, k: int, max_items: int,
+                             out_ids=None, out_counts=None, workspace=None, stream=None):
+    """Top-k search over every part, identical to genie_search_async on one
+    index of all the objects."""
+    import torch
+    nq = d_q_offsets.numel() - 1
+    dev = d_q_offsets.device
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if out_counts is None:
+        out_counts = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = parts.workspace(nq, k, dev)
+    if nq <= 0:
+        return out_ids, out_counts, workspace
+    _check(load().genie_parts_search_async(parts.handle, _dev_ptr(d_q_offsets), _dev_ptr(d_items),
+                                           d_items.numel() // 3, nq, int(max_items), int(k),
+                                           _dev_ptr(out_ids), _dev_ptr(out_counts),
+                                           _dev_ptr(workspace), workspace.numel(),
+                                           _stream_handle(stream)))
+    return out_ids, out_counts, workspace
 
 
 def genie_build_index(values: np.ndarray, n_buckets: int) -> Index:

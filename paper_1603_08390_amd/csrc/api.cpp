@@ -35,8 +35,12 @@ int hip_fail(hipError_t e, const char *what) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint32_t k) {
+    return workspace_layout_tiles(ix->n_tiles, n_queries, k);
+}
+
+WorkspaceLayout workspace_layout_tiles(uint64_t n_tiles, uint32_t n_queries, uint32_t k) {
     WorkspaceLayout L;
-    uint64_t pairs = (uint64_t)n_queries * ix->n_tiles;
+    uint64_t pairs = (uint64_t)n_queries * n_tiles;
     L.status = 0;
     L.tile_kth = 256;
     L.cand = align256(L.tile_kth + pairs * sizeof(uint32_t));
@@ -98,14 +102,14 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
     return genie_build_index_tiled(values, n, d, V, kTileLog2Default, out);
 }
 
-extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
-                                       uint32_t tile_log2, genie_index **out) {
-    clear_error();
-    if (!values || !out) {
+namespace genie {
+
+int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
+                     uint32_t tile_log2, HostIndex *h) {
+    if (!values) {
         set_error("null pointer");
         return GENIE_EINVAL;
     }
-    *out = nullptr;
     if (tile_log2 != 15 && tile_log2 != 16) {
         set_error("tile_log2 must be 15 or 16 (got %u)", tile_log2);
         return GENIE_EINVAL;
@@ -128,9 +132,12 @@ extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint3
     // to an even number of elements with the sentinel id kSentinel so that
     // runs start and end on dword boundaries.  toff = padded offsets, tpad =
     // number of padded runs before each keyword (to recover real lengths).
-    std::vector<uint32_t> toff((uint64_t)T * (nkeys + 1));
-    std::vector<uint32_t> tpad((uint64_t)T * (nkeys + 1));
-    std::vector<uint64_t> tile_size(T), tile_base(T + 1);
+    std::vector<uint32_t> &toff = h->toff, &tpad = h->tpad;
+    toff.assign((uint64_t)T * (nkeys + 1), 0u);
+    tpad.assign((uint64_t)T * (nkeys + 1), 0u);
+    std::vector<uint64_t> tile_size(T);
+    std::vector<uint64_t> &tile_base = h->tile_base;
+    tile_base.assign(T + 1, 0);
     std::atomic<int> bad{0};
     std::atomic<uint32_t> next{0};
     auto count_tiles = [&]() {
@@ -180,7 +187,8 @@ extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint3
     for (uint32_t t = 0; t < T; t++)
         tile_base[t + 1] = tile_base[t] + tile_size[t];
     // postings per keyword over all tiles, as a prefix (query features)
-    std::vector<uint64_t> kcum(nkeys + 1, 0);
+    std::vector<uint64_t> &kcum = h->kcum;
+    kcum.assign(nkeys + 1, 0);
     for (uint32_t t = 0; t < T; t++) {
         const uint32_t *row = &toff[(uint64_t)t * (nkeys + 1)];
         const uint32_t *prow = &tpad[(uint64_t)t * (nkeys + 1)];
@@ -190,7 +198,8 @@ extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint3
     for (uint64_t key = 0; key < nkeys; key++)
         kcum[key + 1] += kcum[key];
     const uint64_t stored = tile_base[T];
-    std::vector<uint16_t> post(stored, kSentinel);
+    std::vector<uint16_t> &post = h->post;
+    post.assign(stored, kSentinel);
     next.store(0);
     auto fill_tiles = [&]() {
         std::vector<uint32_t> fill(nkeys);
@@ -216,7 +225,37 @@ extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint3
         for (auto &th : pool)
             th.join();
     }
+    h->n = n;
+    h->d = d;
+    h->V = V;
+    h->n_tiles = T;
+    h->tile_log2 = tile_log2;
+    h->nkeys = nkeys;
+    h->n_postings = npost;
+    return GENIE_OK;
+}
 
+}  // namespace genie
+
+extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
+                                       uint32_t tile_log2, genie_index **out) {
+    clear_error();
+    if (!values || !out) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    *out = nullptr;
+    HostIndex h;
+    int brc = build_host_index(values, n, d, V, tile_log2, &h);
+    if (brc)
+        return brc;
+    const uint32_t kTile = tile_objects_of(tile_log2);
+    const uint32_t T = h.n_tiles;
+    const uint64_t nkeys = h.nkeys, npost = h.n_postings;
+    const uint64_t stored = h.tile_base[T];
+    const std::vector<uint16_t> &post = h.post;
+    const std::vector<uint64_t> &tile_base = h.tile_base, &kcum = h.kcum;
+    const std::vector<uint32_t> &toff = h.toff, &tpad = h.tpad;
     genie_index *ix = new (std::nothrow) genie_index;
     if (!ix) {
         set_error("host allocation failed");

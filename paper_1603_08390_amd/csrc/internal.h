@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "genie.h"
 
@@ -56,6 +57,17 @@ struct genie_index {
 
 namespace genie {
 
+// An index built in host memory (the layout of genie_index's device arrays).
+struct HostIndex {
+    uint64_t n = 0, nkeys = 0, n_postings = 0;
+    uint32_t d = 0, V = 0, n_tiles = 0, tile_log2 = 0;
+    std::vector<uint16_t> post;
+    std::vector<uint64_t> tile_base, kcum;
+    std::vector<uint32_t> toff, tpad;
+};
+int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
+                     uint32_t tile_log2, HostIndex *h);
+
 void set_error(const char *fmt, ...);
 void clear_error();
 int hip_fail(hipError_t e, const char *what);
@@ -78,6 +90,7 @@ struct WorkspaceLayout {
 // uint32 word of the status block that counts fallback queries
 constexpr uint32_t kStatusFallbackWord = 10;
 WorkspaceLayout workspace_layout(const genie_index *ix, uint32_t n_queries, uint32_t k);
+WorkspaceLayout workspace_layout_tiles(uint64_t n_tiles, uint32_t n_queries, uint32_t k);
 
 // Counter width and table sizes picked for one search call.
 struct SearchShape {
@@ -93,6 +106,27 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
                   size_t workspace_bytes, hipStream_t stream, const float *d_gate = nullptr,
                   float gate_delta = 0.0f, const uint32_t *d_rows = nullptr);
+
+// Multiple loadings: device arrays of one index part (in a streaming slot),
+// scanned into columns [tile_off, tile_off + n_tiles) of candidate rows of
+// tiles_total tiles, with object ids offset by id_base; one merge over all
+// columns afterwards.
+struct IndexView {
+    const uint16_t *post = nullptr;
+    const uint64_t *tile_base = nullptr;
+    const uint32_t *toff = nullptr, *tpad = nullptr;
+    uint64_t n = 0, nkeys = 0;
+    uint32_t d = 0, V = 0, n_tiles = 0, tile_log2 = 0;
+    int scan_threads = kScanThreadsDefault, scan_unroll = kScanUnrollDefault;
+};
+int launch_clear_status(void *d_workspace, hipStream_t stream);
+int launch_part_scan(const IndexView &v, uint64_t id_base, uint32_t tile_off,
+                     uint32_t tiles_total, const uint64_t *d_q_offsets, const genie_item *d_items,
+                     uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k,
+                     void *d_workspace, hipStream_t stream);
+int launch_part_merge(uint64_t n_total, uint32_t tiles_total, uint32_t n_queries, uint32_t k,
+                      void *d_workspace, uint32_t *d_out_ids, uint32_t *d_out_counts,
+                      hipStream_t stream);
 
 // Opt-in kernel timing (timing.cpp): begin returns an event handle or null.
 void *timing_begin(hipStream_t st);

@@ -43,6 +43,12 @@ struct ScanParams {
     const uint32_t *qlist;  // query of each row (fallback pass) or null
     const uint32_t *qcount; // rows in qlist (device) or null
     uint32_t *work;         // persistent schedule: 8 per-XCD pair counters (zeroed), or null
+    // Index parts searched one after another into one candidate array
+    // (multiple loadings): ids of this part start at id_base, its tiles at
+    // column tile_off of rows of tiles_total tiles.  A single index: 0, 0,
+    // n_tiles.
+    uint64_t id_base;
+    uint32_t tile_off, tiles_total;
 };
 
 struct MergeParams {
@@ -301,7 +307,8 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     }
     __syncthreads();
 
-    const uint64_t row = (uint64_t)q * p.n_tiles + t;
+    const uint64_t row = (uint64_t)q * p.tiles_total + p.tile_off + t;
+    const uint64_t gid0 = p.id_base + tile0;   // global id of the tile's first object
     if (too_many) {
         // counts could overflow the packed width: answer with padding only
         if (tid == 0)
@@ -520,7 +527,7 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
             return;
         const uint32_t pos = lds_add(&misc[M_NABOVE], 1);
         if (pos < kk)
-            out[pos] = make_key(old, (uint32_t)(tile0 + lid));
+            out[pos] = make_key(old, (uint32_t)(gid0 + lid));
     };
     if (!misc[M_OVERFLOW]) {
         for (uint32_t slot = tid; slot < cap; slot += NT) {
@@ -560,7 +567,7 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                 const uint32_t lid = w * CPW + f;
                 if (lid < tile_n && ((word >> (f * BITS)) & MASK) == thr) {
                     if (r < need)
-                        out[n_above + r] = make_key(thr, (uint32_t)(tile0 + lid));
+                        out[n_above + r] = make_key(thr, (uint32_t)(gid0 + lid));
                     r++;
                 }
             }
@@ -774,6 +781,77 @@ int dispatch_scan(int bits, int nt, int u, uint32_t tile_log2, const ScanParams 
 
 }  // namespace
 
+int launch_clear_status(void *d_workspace, hipStream_t stream) {
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, stream,
+                       static_cast<uint32_t *>(d_workspace));
+    GENIE_HIP(hipGetLastError());
+    return GENIE_OK;
+}
+
+int launch_part_scan(const IndexView &v, uint64_t id_base, uint32_t tile_off,
+                     uint32_t tiles_total, const uint64_t *d_q_offsets, const genie_item *d_items,
+                     uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k,
+                     void *d_workspace, hipStream_t stream) {
+    const WorkspaceLayout L = workspace_layout_tiles(tiles_total, n_queries, k);
+    SearchShape shape;
+    int rc = search_shape(max_items, k, v.scan_threads, v.tile_log2, &shape);
+    if (rc)
+        return rc;
+    char *ws = static_cast<char *>(d_workspace);
+    ScanParams sp{};
+    sp.post = v.post;
+    sp.tile_base = v.tile_base;
+    sp.toff = v.toff;
+    sp.tpad = v.tpad;
+    sp.n = v.n;
+    sp.nkeys1 = v.nkeys + 1;
+    sp.d = v.d;
+    sp.V = v.V;
+    sp.n_tiles = v.n_tiles;
+    sp.id_base = id_base;
+    sp.tile_off = tile_off;
+    sp.tiles_total = tiles_total;
+    sp.q_off = d_q_offsets;
+    sp.items = reinterpret_cast<const uint32_t *>(d_items);
+    sp.n_items = n_items;
+    sp.nq = n_queries;
+    sp.k = k;
+    sp.max_items = max_items;
+    sp.ht_log2 = shape.ht_log2;
+    const uint64_t pairs = (uint64_t)n_queries * v.n_tiles;
+    sp.per_xcd = (pairs + 7) / 8;
+    sp.cand = reinterpret_cast<uint64_t *>(ws + L.cand);
+    sp.tile_kth = reinterpret_cast<uint32_t *>(ws + L.tile_kth);
+    sp.status = reinterpret_cast<uint32_t *>(ws + L.status);
+    const uint64_t grid = sp.per_xcd * 8;
+    if (grid > 0x7FFFFFFFull) {
+        set_error("too many (query, tile) pairs in one call");
+        return GENIE_ERANGE;
+    }
+    return dispatch_scan(shape.bits, v.scan_threads, v.scan_unroll, v.tile_log2, sp, false,
+                         shape.lds_bytes, grid, stream);
+}
+
+int launch_part_merge(uint64_t n_total, uint32_t tiles_total, uint32_t n_queries, uint32_t k,
+                      void *d_workspace, uint32_t *d_out_ids, uint32_t *d_out_counts,
+                      hipStream_t stream) {
+    const WorkspaceLayout L = workspace_layout_tiles(tiles_total, n_queries, k);
+    char *ws = static_cast<char *>(d_workspace);
+    MergeParams mp{};
+    mp.cand = reinterpret_cast<uint64_t *>(ws + L.cand);
+    mp.tile_kth = reinterpret_cast<uint32_t *>(ws + L.tile_kth);
+    mp.n = n_total;
+    mp.n_tiles = tiles_total;
+    mp.k = k;
+    mp.out_ids = d_out_ids;
+    mp.out_counts = d_out_counts;
+    void *ev = timing_begin(stream);
+    hipLaunchKernelGGL(merge_kernel<256>, dim3(n_queries), dim3(256), 0, stream, mp);
+    timing_end(ev, stream, 1);
+    GENIE_HIP(hipGetLastError());
+    return GENIE_OK;
+}
+
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
@@ -802,6 +880,9 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.d = ix->d;
     sp.V = ix->V;
     sp.n_tiles = ix->n_tiles;
+    sp.id_base = 0;
+    sp.tile_off = 0;
+    sp.tiles_total = ix->n_tiles;
     sp.q_off = d_q_offsets;
     sp.items = reinterpret_cast<const uint32_t *>(d_items);
     sp.n_items = n_items;
