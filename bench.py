@@ -196,6 +196,7 @@ class SearchBench:
         # each path may have its own scan shape (set before its timed steps)
         self.plain_shape = None
         self.gate_shape = None
+        self.spq = True
         self.set_gate_index(ix)
 
     def set_gate_index(self, gix):
@@ -278,6 +279,26 @@ class SearchBench:
             el_plain = self.timed(replay, steps, warmup)
             if not (torch.equal(self.ids, ref[0]) and torch.equal(self.cts, ref[1])):
                 raise RuntimeError("graph replay and eager answers differ")
+        # GEN-SPQ ablation (Section 6.3): the same counters without the Gate
+        # and the Hash Table; eager steps, against the eager plain c-PQ steps
+        spq = None
+        if self.spq:
+            sids, scts = torch.empty_like(self.ids), torch.empty_like(self.cts)
+            sws = g.alloc_workspace(self.ix, self.nq, self.k)
+
+            def spq_step():
+                st = torch.cuda.current_stream()
+                off, items = self.prep(st)
+                g.genie_search_spq_async(self.ix, off, items, self.k, self.max_items, sids, scts,
+                                         sws, st)
+
+            el_spq = self.timed(spq_step, steps, warmup)
+            if not (torch.equal(sids, ref[0]) and torch.equal(scts, ref[1])):
+                raise RuntimeError("GEN-SPQ and c-PQ answers differ")
+            spq = {"value": round(self.nq * steps / el_spq, 1),
+                   "ms_per_step": round(el_spq * 1e3 / steps, 4),
+                   "cpq_speedup": round(el_spq / eager_plain, 4), "identical_results": True}
+            log("GEN-SPQ, eager:", spq["ms_per_step"], "ms per step")
         el_gate, gstats, gkt, eager_gate = None, None, None, None
         if self.model is not None:
             if self.gate_shape:
@@ -349,7 +370,7 @@ class SearchBench:
                        "scan_shape": "%dx%d" % tuple(self.gix.info.scan_shape),
                        "schedule": "persistent" if self.gix.info.scan_persistent else "grid"}
         return {"value": round(nq * steps / elapsed, 1),
-                "ms_per_step": round(elapsed * 1e3 / steps, 4),
+                "ms_per_step": round(elapsed * 1e3 / steps, 4), "gen_spq": spq,
                 "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
                 "launch": "HIP graph replay" if graph else "eager",
                 "roofline": roofline, "atomic_roof": atomic_roof,
@@ -368,7 +389,7 @@ def line(args, workload, res, config, dtype="u32"):
            "vs_baseline": None, "dtype": dtype, "data": "synthetic",
            "config": dict(config, path=res["path"], launch=res["launch"],
                           parallelism="single GPU")}
-    for key in ("roofline", "atomic_roof", "plain_cpq", "learned_gate"):
+    for key in ("roofline", "atomic_roof", "plain_cpq", "learned_gate", "gen_spq"):
         out[key] = res[key]
     out["roofline"]["traffic"] = measured_traffic(workload)
     return out

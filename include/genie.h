@@ -217,6 +217,24 @@ int genie_search_gated_async(const genie_index *ix, const uint64_t *d_q_offsets,
                              void *d_workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * GEN-SPQ, the c-PQ ablation of Section 6.3: the same index and counters,
+ * but without the Gate and the Hash Table of Section 3.3.  Every posting
+ * only increments its object's counter; afterwards each tile finds its k-th
+ * count from the exact counters (the largest c with at least min(k, tile
+ * objects) objects of count >= c, found by bisection: the bucket selection
+ * of the paper's appendix collapses to this on small integer counts) and
+ * selects from the counters alone.  Results are identical to
+ * genie_search_async; it exists to measure what c-PQ saves.  Arguments,
+ * workspace and errors as genie_search_async (it always runs 1024 threads
+ * x 4 dwords, one workgroup per pair).
+ */
+int genie_search_spq_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                           const genie_item *d_items, uint64_t n_items, uint32_t n_queries,
+                           uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                           uint32_t *d_out_counts, void *d_workspace, size_t workspace_bytes,
+                           void *stream);
+
+/*
  * genie_search_async (d_gate NULL) or genie_search_gated_async (d_gate set)
  * over the first *d_rows of a batch laid out for `capacity` queries, the
  * count read on the device when the kernels run.  For callers that record

@@ -16,7 +16,7 @@ Contents (each function names the passage of the paper it follows):
 * ``lsh_signatures`` -- E2LSH (Equation of Section 4.2.3) followed by the
   re-hash r_i (Section 4.1.2), in float64 (O4).
 * ``exact_knn_l2`` / ``recall`` / ``approximation_ratio`` -- exact l2
-  neighbours and the approximation ratio of Section 6.3.1 (O5).
+  neighbours and the approximation ratio of Section 6.4.1 (O5).
 
 Answer order everywhere: count descending, then id ascending (the paper
 breaks ties randomly; a fixed total order makes the answer unique).  Rows
@@ -303,7 +303,7 @@ def lsh_signatures(points, a, b, w, rehash_params, log2_buckets,
 
 
 # ----------------------------------------------------------------------------
-# O5: exact l2 neighbours, recall and approximation ratio (Section 6.3.1)
+# O5: exact l2 neighbours, recall and approximation ratio (Section 6.4.1)
 # ----------------------------------------------------------------------------
 
 def exact_knn_l2(points: np.ndarray, queries: np.ndarray, k: int,
@@ -342,7 +342,7 @@ def recall(found_ids: np.ndarray, true_ids: np.ndarray) -> float:
 def approximation_ratio(points: np.ndarray, queries: np.ndarray, found_ids: np.ndarray,
                         true_dist: np.ndarray) -> float:
     """(1/k) sum_i ||p_i - q|| / ||p*_i - q|| with both lists sorted by distance
-    (Section 6.3.1), averaged over queries; pairs with a zero true distance
+    (Section 6.4.1), averaged over queries; pairs with a zero true distance
     are skipped."""
     ratios = []
     for q, f, td in zip(queries, found_ids, true_dist):

@@ -43,7 +43,7 @@ EXPORTED = (
     "genie_gate_adam_async", "genie_lsh_items_async", "genie_index_set_scan_shape",
     "genie_index_set_scan_schedule", "genie_search_rows_async", "genie_parts_build",
     "genie_parts_free", "genie_parts_info_get", "genie_parts_workspace_size",
-    "genie_parts_search_async",
+    "genie_parts_search_async", "genie_search_spq_async",
 )
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
@@ -117,6 +117,8 @@ def load() -> ctypes.CDLL:
     lib.genie_search_rows_async.argtypes = [vp, vp, vp, u64, u32, vp, u32, u32, vp, f32, vp, vp,
                                             vp, sz, vp]
     lib.genie_search_rows_async.restype = ctypes.c_int
+    lib.genie_search_spq_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, vp, vp, sz, vp]
+    lib.genie_search_spq_async.restype = ctypes.c_int
     lib.genie_parts_build.argtypes = [vp, u64, u32, u32, u64, u32, ctypes.POINTER(vp)]
     lib.genie_parts_build.restype = ctypes.c_int
     lib.genie_parts_free.argtypes = [vp]
@@ -403,6 +405,30 @@ def genie_search_gated_async(index: Index, d_q_offsets, d_items, k: int, max_ite
                                            _dev_ptr(d_gate), float(gate_delta), _dev_ptr(out_ids),
                                            _dev_ptr(out_counts), _dev_ptr(workspace),
                                            workspace.numel(), _stream_handle(stream)))
+    return out_ids, out_counts, workspace
+
+
+def genie_search_spq_async(index: Index, d_q_offsets, d_items, k: int, max_items: int,
+                           out_ids=None, out_counts=None, workspace=None, stream=None):
+    """GEN-SPQ ablation: count every posting, then select from the exact
+    counters (no Gate, no Hash Table); identical results to
+    genie_search_async."""
+    import torch
+    nq = d_q_offsets.numel() - 1
+    dev = d_q_offsets.device
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if out_counts is None:
+        out_counts = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = alloc_workspace(index, nq, k, dev)
+    if nq <= 0:
+        return out_ids, out_counts, workspace
+    _check(load().genie_search_spq_async(index.handle, _dev_ptr(d_q_offsets), _dev_ptr(d_items),
+                                         d_items.numel() // 3, nq, int(max_items), int(k),
+                                         _dev_ptr(out_ids), _dev_ptr(out_counts),
+                                         _dev_ptr(workspace), workspace.numel(),
+                                         _stream_handle(stream)))
     return out_ids, out_counts, workspace
 
 

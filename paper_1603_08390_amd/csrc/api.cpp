@@ -446,6 +446,21 @@ extern "C" int genie_search_gated_async(const genie_index *ix, const uint64_t *d
                          (hipStream_t)stream, d_gate, gate_delta);
 }
 
+extern "C" int genie_search_spq_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                                      const genie_item *d_items, uint64_t n_items,
+                                      uint32_t n_queries, uint32_t max_items, uint32_t k,
+                                      uint32_t *d_out_ids, uint32_t *d_out_counts,
+                                      void *d_workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = check_async(ix, d_q_offsets, d_items, n_queries, max_items, k, d_out_ids,
+                         d_out_counts, d_workspace);
+    if (rc || n_queries == 0)
+        return rc;
+    return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, k, d_out_ids,
+                         d_out_counts, nullptr, d_workspace, workspace_bytes,
+                         (hipStream_t)stream, nullptr, 0.0f, nullptr, true);
+}
+
 extern "C" int genie_search_rows_async(const genie_index *ix, const uint64_t *d_q_offsets,
                                        const genie_item *d_items, uint64_t n_items,
                                        uint32_t capacity, const uint32_t *d_rows,

@@ -105,7 +105,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
                   size_t workspace_bytes, hipStream_t stream, const float *d_gate = nullptr,
-                  float gate_delta = 0.0f, const uint32_t *d_rows = nullptr);
+                  float gate_delta = 0.0f, const uint32_t *d_rows = nullptr,
+                  bool spq = false);
 
 // Multiple loadings: device arrays of one index part (in a streaming slot),
 // scanned into columns [tile_off, tile_off + n_tiles) of candidate rows of

@@ -49,6 +49,7 @@ struct ScanParams {
     // n_tiles.
     uint64_t id_base;
     uint32_t tile_off, tiles_total;
+    uint32_t spq;           // 1: GEN-SPQ ablation (count everything, then select)
 };
 
 struct MergeParams {
@@ -210,7 +211,7 @@ constexpr int scan_waves_per_eu() {
 // One (query, tile) pair: the whole of Algorithm 1 over the tile's part of
 // the query's lists, then the tile's exact top-k.  `bc` is the workgroup's
 // static counter array; `smem` the dynamic LDS block.
-template <int BITS, int NT, int U, bool DUMP, int LG>
+template <int BITS, int NT, int U, bool DUMP, int LG, bool SPQ = false>
 __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, uint32_t *bc,
                                           uint32_t *smem) {
     static_assert(BITS == 4 || BITS == 8 || BITS == 16, "power-of-two counter width");
@@ -427,12 +428,20 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                 }
                 uint32_t inc;   // 1 << (sh mod 32): the shift unit masks the amount
                 asm("v_lshlrev_b32 %0, %1, 1" : "=v"(inc) : "v"(sh));
-                const uint32_t old = lds_add(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(bc) + a), inc);
-                f[2 * u + h] = __builtin_amdgcn_ubfe(old, sh, BITS);
+                uint32_t *cw = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(bc) + a);
+                if constexpr (SPQ) {   // count only: no value returned, no gate
+                    __hip_atomic_fetch_add(cw, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    f[2 * u + h] = 0;
+                } else {
+                    const uint32_t old = lds_add(cw, inc);
+                    f[2 * u + h] = __builtin_amdgcn_ubfe(old, sh, BITS);
+                }
             }
         }
         // Algorithm 1's gate check, first for the whole wave at once: the
         // largest previous count of the lane's postings against AT - 1
+        if constexpr (SPQ)
+            continue;
         uint32_t fmax = f[0];
 #pragma unroll
         for (int j = 1; j < 2 * U; j++)
@@ -485,16 +494,48 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     if (lane == 0 && passes)
         lds_add(&misc[M_PASSES], passes);
     __syncthreads();
+    uint32_t spq_thr = 0;
+    if constexpr (SPQ) {
+        // GEN-SPQ (the c-PQ ablation of Section 6.3): the counters hold every
+        // exact count; the tile's k-th count is found by bisection over them
+        // (the largest c with at least min(k, tile_n) objects of count >= c,
+        // 0 when fewer objects than that were hit), and selection below then
+        // reads the counters alone, as after a Hash Table overflow.
+        const uint32_t kk_t = min(p.k, tile_n);
+        uint32_t lo = 0, hi = s;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) / 2;
+            uint32_t mine = 0;
+            for (uint32_t w = tid; w < NW; w += NT) {
+                const uint32_t word = bc[w];
+#pragma unroll
+                for (uint32_t fi = 0; fi < CPW; fi++)
+                    mine += (w * CPW + fi < tile_n && ((word >> (fi * BITS)) & MASK) >= mid) ? 1u
+                                                                                            : 0u;
+            }
+            uint32_t total = 0;
+            block_exclusive_scan<NT>(mine, misc + M_WAVESUM, &total);
+            if (total >= kk_t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        spq_thr = lo;
+    }
     if (tid == 0) {
         // settle: AT advances that raced with ZA increments are finished here
         uint32_t a = misc[M_AT];
         while (a <= s && za[a] >= k)
             a++;
+        if constexpr (SPQ) {
+            a = spq_thr + 1;
+            misc[M_OVERFLOW] = 1;   // select from the counters
+        }
         misc[M_AT] = a;
         const uint64_t scanned = misc[M_SCANNED];
         unsigned long long *stats = reinterpret_cast<unsigned long long *>(p.status + 2);
         atomicAdd(&stats[0], (unsigned long long)scanned);
-        if (misc[M_OVERFLOW])
+        if (misc[M_OVERFLOW] && !SPQ)
             atomicAdd(&stats[1], 1ull);
         atomicAdd(&stats[2], (unsigned long long)misc[M_INSERTS]);
         atomicAdd(&stats[3], (unsigned long long)misc[M_PASSES]);
@@ -579,7 +620,7 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         p.tile_kth[row] = thr;
 }
 
-template <int BITS, int NT, int U, bool DUMP, int LG, bool PERSIST>
+template <int BITS, int NT, int U, bool DUMP, int LG, bool PERSIST, bool SPQ = false>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<BITS, NT, LG>())))
 void scan_cpq_kernel(ScanParams p) {
@@ -597,7 +638,7 @@ void scan_cpq_kernel(ScanParams p) {
     if constexpr (!PERSIST) {   // one workgroup per pair
         const uint64_t pair = (uint64_t)(bid & 7) * p.per_xcd + (bid >> 3);
         if (pair < npairs)
-            scan_pair<BITS, NT, U, DUMP, LG>(p, pair, bc, smem);
+            scan_pair<BITS, NT, U, DUMP, LG, SPQ>(p, pair, bc, smem);
     } else {
         // Persistent schedule: as many workgroups as fit the device at once,
         // each taking the next pair of its XCD's slice from that slice's
@@ -619,7 +660,7 @@ void scan_cpq_kernel(ScanParams p) {
                 spent++;
                 continue;
             }
-            scan_pair<BITS, NT, U, DUMP, LG>(p, first + idx, bc, smem);
+            scan_pair<BITS, NT, U, DUMP, LG, SPQ>(p, first + idx, bc, smem);
             __syncthreads();   // the next pair reuses the LDS
         }
     }
@@ -724,10 +765,12 @@ template <int BITS, int NT, int U, int LG>
 int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipStream_t st) {
     // the count dump (match-count entry point) always runs 1024 x 4, one
     // workgroup per pair
+    // (the GEN-SPQ ablation likewise)
     const void *kern = dump ? (const void *)scan_cpq_kernel<BITS, 1024, 4, true, LG, false>
+                     : sp.spq ? (const void *)scan_cpq_kernel<BITS, 1024, 4, false, LG, false, true>
                      : sp.work ? (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, true>
                                : (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, false>;
-    const int nt = dump ? 1024 : NT;
+    const int nt = (dump || sp.spq) ? 1024 : NT;
     GENIE_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (sp.work && !dump) {
         // persistent schedule: the workgroups that fit the device at once
@@ -856,7 +899,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
                   uint32_t *d_out_counts, uint32_t *d_full_counts, void *d_workspace,
                   size_t workspace_bytes, hipStream_t stream, const float *d_gate,
-                  float gate_delta, const uint32_t *d_rows) {
+                  float gate_delta, const uint32_t *d_rows, bool spq) {
     const bool dump = d_full_counts != nullptr;
     const WorkspaceLayout L = workspace_layout(ix, n_queries, k);
     if (workspace_bytes < L.total) {
@@ -865,7 +908,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
         return GENIE_EINVAL;
     }
     SearchShape shape;
-    const int threads = dump ? 1024 : ix->scan_threads;   // the count dump runs 1024 x 4
+    // the count dump and the GEN-SPQ ablation run 1024 x 4
+    const int threads = (dump || spq) ? 1024 : ix->scan_threads;
     int rc = search_shape(max_items, k, threads, ix->tile_log2, &shape);
     if (rc)
         return rc;
@@ -898,7 +942,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.status = reinterpret_cast<uint32_t *>(ws + L.status);
     sp.gate = d_gate;
     sp.gate_delta = gate_delta;
-    sp.work = (ix->scan_persistent && !dump) ? sp.status + kWorkWord : nullptr;
+    sp.spq = spq ? 1u : 0u;
+    sp.work = (ix->scan_persistent && !dump && !spq) ? sp.status + kWorkWord : nullptr;
     sp.qcount = d_rows;   // live rows (device), or null: all n_queries
     const uint64_t grid = sp.per_xcd * 8;
     if (grid > 0x7FFFFFFFull) {

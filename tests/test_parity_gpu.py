@@ -258,3 +258,35 @@ def test_ann_search_on_shared_signatures():
     qsig = oracle.lsh_signatures(inp.queries, inp.a, inp.b, inp.w, inp.rehash, inp.log2_buckets)
     q = workloads.queries_exact(qsig)
     _check(sig, 1 << inp.log2_buckets, q, inp.k)
+
+
+# GEN-SPQ ablation (no Gate, no Hash Table; the k-th count by bisection over
+# the exact counters): the same answers at every counter width, both tilings
+# and k > n.
+@pytest.mark.parametrize("case", ["relational", "uneven", "tiles15", "small"])
+def test_gen_spq_ablation_equals_oracle(case):
+    print("gen-spq", case, flush=True)
+    if case == "relational":
+        inst = workloads.relational(n=3 * 65535 + 77, d=20, V=40, nq=40, k=100)
+        lg, k = 16, 100
+    elif case == "uneven":
+        inst = workloads.uneven(n=100_000, d=16, V=64, nq=16, smin=100, smax=400)
+        lg, k = 16, 100
+    elif case == "tiles15":
+        inst = workloads.relational(n=4 * 32767 + 5, d=12, V=16, nq=30, k=10)
+        lg, k = 15, 10
+    else:
+        inst = workloads.relational(n=900, d=6, V=10, nq=8, k=1000)
+        lg, k = 16, 1000
+    ix = genie.Index(inst.values, inst.V, lg)
+    off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
+    ids, cts, ws = genie.genie_search_spq_async(ix, off, items, k, inst.queries.max_items())
+    torch.cuda.synchronize()
+    o_ids, o_cts, _, scanned = oracle.search_idx(oracle.build_csr(inst.values, inst.V),
+                                                 inst.queries, k)
+    st = genie.workspace_stats(ws)
+    assert st["status"] == 0 and st["gate_passes"] == 0 and st["ht_inserts"] == 0
+    assert st["postings_scanned"] == int(scanned.sum())
+    assert np.array_equal(genie.as_uint32(ids), o_ids)
+    assert np.array_equal(genie.as_uint32(cts), o_cts)
+    ix.free()
