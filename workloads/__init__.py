@@ -32,7 +32,7 @@ from typing import Optional
 import numpy as np
 
 BASE_SEED = 1603083900
-CONFIG_IDS = {"tiny": 1, "relational": 2, "ann": 3, "uneven": 4, "serving": 5}
+CONFIG_IDS = {"tiny": 1, "relational": 2, "ann": 3, "uneven": 4, "serving": 5, "laplace": 6}
 
 
 def rng_streams(config_id: int, salt: int = 0):
@@ -229,14 +229,7 @@ def ann(n: int = 1_000_000, dim: int = 128, nq: int = 4096, m: int = 237,
         sigma: float = 0.5, qsigma: float = 0.1, k: int = 100,
         salt: int = 0, chunk_rows: int = 1 << 18) -> AnnInputs:
     ro, rq, rl = rng_streams(CONFIG_IDS["ann"], salt)
-    means = ro.uniform(0.0, 8.0, size=(components, dim)).astype(np.float32)
-    points = np.empty((n, dim), dtype=np.float32)
-    for r0 in range(0, n, chunk_rows):
-        r1 = min(n, r0 + chunk_rows)
-        comp = ro.integers(0, components, size=r1 - r0)
-        x = means[comp] + np.float32(sigma) * ro.standard_normal((r1 - r0, dim), dtype=np.float32)
-        np.maximum(x, 0.0, out=x)
-        points[r0:r1] = x
+    points = gmm_points(ro, n, dim, components, sigma, chunk_rows)
     queries = ann_queries(rq, points, nq, qsigma)
     a = rl.standard_normal((m, dim), dtype=np.float32)
     b = rl.uniform(0.0, w, size=m).astype(np.float32)
@@ -248,6 +241,59 @@ def ann(n: int = 1_000_000, dim: int = 128, nq: int = 4096, m: int = 237,
     rehash[0::2] = A
     rehash[1::2] = B
     return AnnInputs(points, queries, a, b, float(w), rehash, int(log2_buckets), k)
+
+
+def gmm_points(rng, n: int, dim: int, components: int = 64, sigma: float = 0.5,
+               chunk_rows: int = 1 << 18) -> np.ndarray:
+    """Equal-weight Gaussian mixture: means U[0, 8)^dim, per-coordinate sigma,
+    clipped at 0 (non-negative features)."""
+    means = rng.uniform(0.0, 8.0, size=(components, dim)).astype(np.float32)
+    points = np.empty((n, dim), dtype=np.float32)
+    for r0 in range(0, n, chunk_rows):
+        r1 = min(n, r0 + chunk_rows)
+        comp = rng.integers(0, components, size=r1 - r0)
+        x = means[comp] + np.float32(sigma) * rng.standard_normal((r1 - r0, dim), dtype=np.float32)
+        np.maximum(x, 0.0, out=x)
+        points[r0:r1] = x
+    return points
+
+
+@dataclasses.dataclass
+class LaplaceInputs:
+    points: np.ndarray     # float32 [n, dim]
+    queries: np.ndarray    # float32 [nq, dim]
+    g: np.ndarray          # float32 [m, dim] grid pitch per function and dimension
+    u: np.ndarray          # float32 [m, dim] grid shift, in [0, g)
+    seeds: np.ndarray      # uint32 [m] MurmurHash3 seed per function
+    sigma: float
+    log2_buckets: int
+    k: int
+
+
+def rbh_params(rng, m: int, dim: int, sigma: float):
+    """Random binning functions for the Laplacian kernel exp(-||.||_1 / sigma):
+    pitch ~ Gamma(2, sigma) and shift ~ U[0, pitch) per function and
+    dimension, and a 32-bit re-hash seed per function."""
+    g = rng.gamma(2.0, sigma, size=(m, dim)).astype(np.float32)
+    g = np.maximum(g, np.float32(1e-6))
+    u = (rng.random((m, dim)) * g).astype(np.float32)
+    u = np.minimum(u, np.nextafter(g, np.float32(0)))
+    seeds = rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32)
+    return g, u, seeds
+
+
+def laplace(n: int = 1_000_000, dim: int = 128, nq: int = 4096, m: int = 237,
+            sigma: float = 32.0, log2_buckets: int = 13, components: int = 64,
+            csigma: float = 0.5, qsigma: float = 0.1, k: int = 100, salt: int = 0,
+            chunk_rows: int = 1 << 18) -> LaplaceInputs:
+    """ANN in the Laplacian kernel space (Section 4.1.3): the Gaussian-mixture
+    points of ``ann`` searched through m RBH functions re-hashed into
+    2^log2_buckets buckets.  Stands in for the OCR workload of the paper."""
+    ro, rq, rl = rng_streams(CONFIG_IDS["laplace"], salt)
+    points = gmm_points(ro, n, dim, components, csigma, chunk_rows)
+    queries = ann_queries(rq, points, nq, qsigma)
+    g, u, seeds = rbh_params(rl, m, dim, sigma)
+    return LaplaceInputs(points, queries, g, u, seeds, float(sigma), int(log2_buckets), k)
 
 
 def ann_queries(rng, points: np.ndarray, nq: int, qsigma: float = 0.1) -> np.ndarray:
