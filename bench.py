@@ -25,6 +25,9 @@ Workloads (--workload):
               16,384 queries of 4..512 items in one launch, k = 100; the
               index tiling and the scan shape are picked by the autotuner
               first.
+  laplace     ANN in the Laplacian kernel space: the ann points through 237
+              RBH functions (sigma = 32) re-hashed by MurmurHash3 into 8,192
+              buckets; hashing in the step; recall against exact L1.
   multiload   8,000,000 relational objects whose index streams to the device
               in 4 parts per batch (multiple loadings), against one resident
               index of the same objects.
@@ -70,6 +73,8 @@ METRICS = {
     "uneven": "queries/sec at k=100, 10M objects, 16,384 uneven queries in one launch; "
               "learned-gate vs plain c-PQ",
     "multiload": "queries/sec at k=100, 8M objects, index streamed in 4 parts per batch",
+    "laplace": "queries/sec at k=100, Laplacian-kernel ANN via RBH, 1M points x 128-d, hashing "
+               "included; learned-gate vs plain c-PQ",
     "serving": "queries/sec and p50/p99 latency of the request loop, relational + tau-ANN mix, "
                "k in {10,100,1000}; learned gate off and on",
 }
@@ -589,6 +594,88 @@ def bench_ann(args, torch, genie, workloads):
     return out
 
 
+def laplace_quality(torch, P, Q, found, k, sample=256):
+    """recall@k against exact L1 neighbours (the Laplacian kernel is monotone
+    in the L1 distance) and the L1 approximation ratio, on the first
+    `sample` queries, in float32 on the device (evaluation only)."""
+    Q, found = Q[:sample], found[:sample].long()
+    rows = []
+    for q0 in range(0, Q.shape[0], 16):
+        q = Q[q0:q0 + 16, None, :]
+        rows.append(torch.cat([(q - P[None, c:c + 32768]).abs().sum(-1)
+                               for c in range(0, P.shape[0], 32768)], dim=1))
+    d = torch.cat(rows, dim=0)
+    t_dist, t_ids = torch.topk(d, k, dim=1, largest=False)
+    hit = (found[:, :, None] == t_ids[:, None, :]).any(2).float().mean().item()
+    fd, _ = torch.sort(torch.gather(d, 1, found), dim=1)
+    ok = t_dist > 0
+    r = torch.where(ok, fd / torch.where(ok, t_dist, torch.ones_like(t_dist)),
+                    torch.zeros_like(fd))
+    per_q = r.sum(1) / ok.sum(1).clamp_min(1)
+    return hit, per_q[ok.any(1)].mean().item()
+
+
+def bench_laplace(args, torch, genie, workloads):
+    """ANN in the Laplacian kernel space (Section 4.1.3): the Gaussian-mixture
+    points through 237 RBH functions re-hashed by MurmurHash3; a step hashes
+    the query points (RBH kernel), forms their items and searches."""
+    inp = workloads.laplace()
+    log("laplace generated")
+    g = torch.from_numpy(inp.g).cuda()
+    u = torch.from_numpy(inp.u).cuda()
+    seeds = torch.from_numpy(inp.seeds.view(np.int32)).cuda()
+    sig = genie.genie_rbh_signatures(torch.from_numpy(inp.points).cuda(), g, u, seeds,
+                                     inp.log2_buckets)
+    torch.cuda.synchronize()
+    sig_h = genie.as_uint32(sig)
+    del sig
+    ix = genie.Index(sig_h, 1 << inp.log2_buckets)
+    log("laplace index ready:", ix.info)
+    nq, m, k = inp.queries.shape[0], inp.g.shape[0], inp.k
+    qpts = torch.from_numpy(inp.queries).cuda()
+    qsig = torch.empty((nq, m), dtype=torch.int32, device="cuda")
+    qoff = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    qitems = torch.empty((nq * m, 3), dtype=torch.int32, device="cuda")
+
+    def prep(st):
+        genie.genie_rbh_signatures(qpts, g, u, seeds, inp.log2_buckets, out=qsig, stream=st)
+        genie.genie_lsh_items_async(qsig, out=(qoff, qitems), stream=st)
+        return qoff, qitems
+
+    sb = SearchBench(genie, torch, ix, nq, k, m, prep)
+    if not args.no_gate:
+        tq = workloads.ann_queries(np.random.default_rng(workloads.BASE_SEED + 106),
+                                   inp.points, args.gate_train_queries)
+        tsig = genie.genie_rbh_signatures(torch.from_numpy(tq).cuda(), g, u, seeds,
+                                          inp.log2_buckets)
+        toff, titems = genie.genie_lsh_items_async(tsig)
+        sb.model = train_gate(genie, torch, ix, [(toff, titems, m, k)], args.gate_epochs)
+    res = sb.run(args.steps, args.warmup, nq * m, graph=use_graph(args, "laplace"))
+    P = torch.from_numpy(inp.points).cuda()
+    rec, ratio = laplace_quality(torch, P, qpts, sb.ids, k)
+    out = line(args, "laplace", res, {
+        "workload": "Laplacian-kernel ANN: 1,000,000 float32 points x 128 (64-component "
+                    "Gaussian mixture, clipped at 0); 237 RBH functions (sigma=32), "
+                    "MurmurHash3 re-hash into 8,192 buckets; 4,096 perturbed query points; "
+                    "k=100",
+        "n_objects": inp.points.shape[0], "n_functions": m, "n_buckets": 1 << inp.log2_buckets,
+        "n_queries": nq, "k": k})
+    out["quality"] = {"recall_at_100": round(rec, 4), "l1_approximation_ratio": round(ratio, 4),
+                      "queries": 256, "truth": "exact L1, float32 on the device"}
+    if out["learned_gate"]:
+        out["learned_gate"].update(train_queries=args.gate_train_queries,
+                                   epochs=args.gate_epochs)
+    if not args.no_cpu_baseline and args.cpu_budget > 0:
+        qs = workloads.queries_exact(genie.as_uint32(qsig))
+        cb = cpu_baseline(sig_h, 1 << inp.log2_buckets, qs, k, args.cpu_budget)
+        cb["sample"] += "; query signatures from the timed run, hashing not included"
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
+    ix.free()
+    return out
+
+
 def bench_multiload(args, torch, genie, workloads):
     """Multiple loadings (Section 3.4): 8,000,000 relational objects whose
     index is streamed to the device in four parts of 2,000,000 on every batch
@@ -907,7 +994,7 @@ def main():
         return
     fn = {"relational": bench_relational, "tiny": bench_tiny, "ann": bench_ann,
           "uneven": bench_uneven, "serving": bench_serving,
-          "multiload": bench_multiload}[args.workload]
+          "multiload": bench_multiload, "laplace": bench_laplace}[args.workload]
     print(json.dumps(fn(args, torch, genie, workloads)), flush=True)
 
 

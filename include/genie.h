@@ -254,6 +254,25 @@ int genie_search_rows_async(const genie_index *ix, const uint64_t *d_q_offsets,
                             uint32_t *d_out_counts, void *d_workspace, size_t workspace_bytes,
                             void *stream);
 
+/*
+ * Random binning hashing (RBH) signatures for ANN in the Laplacian kernel
+ * space (Section 4.1.3): for every point p and function f, the bin
+ * floor((p_j - u[f][j]) / g[f][j]) on every dimension j (float32, correctly
+ * rounded division; clamped to int32), the bin vector taken as int32
+ * blocks in ascending j and re-hashed by MurmurHash3_x86_32 with seed
+ * seeds[f]; out_sig[p][f] = the hash's top log2_buckets bits.  With g drawn
+ * from Gamma(2, sigma) and u uniformly from [0, g) per function and
+ * dimension, two points collide in a function with probability
+ * exp(-||p - q||_1 / sigma).  Each signature depends on its own point and
+ * function only.  Queries then use genie_lsh_items_async as for E2LSH.
+ *   d_points: device, n * dim float32; d_g, d_u: device, m * dim float32
+ *   (g > 0); d_seeds: device, m uint32; d_out_sig: device, n * m uint32.
+ *   1 <= log2_buckets <= 32.  Errors: GENIE_EINVAL.
+ */
+int genie_rbh_signatures(const float *d_points, uint64_t n, uint32_t dim, const float *d_g,
+                         const float *d_u, const uint32_t *d_seeds, uint32_t m,
+                         uint32_t log2_buckets, uint32_t *d_out_sig, void *stream);
+
 /* ---- multiple loadings: an index streamed to the device in parts -------- */
 
 typedef struct genie_parts genie_parts; /* opaque, owned by the library */

@@ -43,7 +43,7 @@ EXPORTED = (
     "genie_gate_adam_async", "genie_lsh_items_async", "genie_index_set_scan_shape",
     "genie_index_set_scan_schedule", "genie_search_rows_async", "genie_parts_build",
     "genie_parts_free", "genie_parts_info_get", "genie_parts_workspace_size",
-    "genie_parts_search_async", "genie_search_spq_async",
+    "genie_parts_search_async", "genie_search_spq_async", "genie_rbh_signatures",
 )
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
@@ -106,6 +106,8 @@ def load() -> ctypes.CDLL:
     lib.genie_lsh_signatures.argtypes = [vp, u64, u32, vp, vp, ctypes.c_float, u32, vp, u32,
                                          vp, vp]
     lib.genie_lsh_signatures.restype = ctypes.c_int
+    lib.genie_rbh_signatures.argtypes = [vp, u64, u32, vp, vp, vp, u32, u32, vp, vp]
+    lib.genie_rbh_signatures.restype = ctypes.c_int
     lib.genie_kernel_timing_enable.argtypes = [ctypes.c_int]
     lib.genie_kernel_timing_enable.restype = ctypes.c_int
     lib.genie_kernel_timing_read.argtypes = [ctypes.POINTER(_KernelTimes), ctypes.c_int]
@@ -550,6 +552,22 @@ def genie_lsh_signatures(d_points, d_a, d_b, w: float, d_rehash, log2_buckets: i
     _check(load().genie_lsh_signatures(_dev_ptr(d_points), n, dim, _dev_ptr(d_a), _dev_ptr(d_b),
                                        float(w), m, _dev_ptr(d_rehash), int(log2_buckets),
                                        _dev_ptr(out), _stream_handle(stream)))
+    return out
+
+
+def genie_rbh_signatures(d_points, d_g, d_u, d_seeds, log2_buckets: int, out=None, stream=None):
+    """RBH signatures [n, m] (uint32 stored in int32) for float32 points on
+    the device (Laplacian kernel, MurmurHash3 re-hash)."""
+    import torch
+    n, dim = d_points.shape
+    m = d_g.shape[0]
+    if d_g.shape != (m, dim) or d_u.shape != (m, dim) or d_seeds.numel() != m:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.int32, device=d_points.device)
+    _check(load().genie_rbh_signatures(_dev_ptr(d_points), n, dim, _dev_ptr(d_g), _dev_ptr(d_u),
+                                       _dev_ptr(d_seeds), m, int(log2_buckets), _dev_ptr(out),
+                                       _stream_handle(stream)))
     return out
 
 
