@@ -17,6 +17,11 @@ Contents (each function names the passage of the paper it follows):
   re-hash r_i (Section 4.1.2), in float64 (O4).
 * ``exact_knn_l2`` / ``recall`` / ``approximation_ratio`` -- exact l2
   neighbours and the approximation ratio of Section 6.4.1 (O5).
+* ``oracle.rbh`` -- random binning hashing for the Laplacian kernel with its
+  MurmurHash3 re-hash (Section 4.1.3).
+* ``oracle.sequence`` -- sequence search with the Shotgun-and-Assembly
+  scheme: ordered n-grams, top-K candidates, Algorithm 2 and the top-k
+  certificate (Section 5.1); edit distance in plain C (edit_distance.c).
 
 Answer order everywhere: count descending, then id ascending (the paper
 breaks ties randomly; a fixed total order makes the answer unique).  Rows
@@ -33,6 +38,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "genie_oracle.c")
+_SRC_ED = os.path.join(_HERE, "edit_distance.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 UINT32_MAX = 0xFFFFFFFF
 
@@ -44,7 +50,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Werror",
-                               "-shared", "-fPIC", _SRC, "-o", tmp])
+                               "-shared", "-fPIC", _SRC, _SRC_ED, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -66,6 +72,11 @@ def _load():
         lib.oracle_match_counts.argtypes = [u64p, u32p, ctypes.c_uint64, ctypes.c_uint32,
                                             ctypes.c_uint32, u32p, ctypes.c_uint64, u32p,
                                             u64p]
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        lib.oracle_edit_distance.argtypes = [u8p, ctypes.c_uint32, u8p, ctypes.c_uint32]
+        lib.oracle_edit_distance.restype = ctypes.c_uint32
+        lib.oracle_edit_distances.argtypes = [u8p, u64p, u64p, u8p, u64p, u64p, ctypes.c_uint64,
+                                              u32p]
         _lib = lib
     return _lib
 

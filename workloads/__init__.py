@@ -20,6 +20,13 @@ Workloads (the paper's datasets are not available; these stand in for them):
                   k = 100.  Stands in for SIFT (Section 6.1.1).
 * ``uneven``      10,000,000 x 64 dims, 1,024 buckets, Zipf(1.1); 16,384
                   queries with 4..512 items each; k = 100.
+* ``laplace``     the ``ann`` points through RBH functions for the Laplacian
+                  kernel (Section 4.1.3); stands in for OCR.
+* ``sequence``    5,000,000 title-like strings (words of a Zipf vocabulary
+                  joined by spaces); 1,024 queries of 40 characters, each a
+                  data string with 20 % of its characters replaced; 3-grams,
+                  K = 32 candidates, k = 1.  Stands in for DBLP titles
+                  (Sections 5.1 and 6.1.1).
 
 Every generator takes explicit sizes so that tests can draw scaled-down
 instances with the same structure.
@@ -32,7 +39,8 @@ from typing import Optional
 import numpy as np
 
 BASE_SEED = 1603083900
-CONFIG_IDS = {"tiny": 1, "relational": 2, "ann": 3, "uneven": 4, "serving": 5, "laplace": 6}
+CONFIG_IDS = {"tiny": 1, "relational": 2, "ann": 3, "uneven": 4, "serving": 5, "laplace": 6,
+              "sequence": 7}
 
 
 def rng_streams(config_id: int, salt: int = 0):
@@ -320,3 +328,139 @@ def random_small(rng, n: int, d: int, V: int, nq: int, max_items: int,
     # hi may be below lo (empty item) and either bound may lie past V-1
     items = np.stack([dims, lo, hi], axis=-1).astype(np.uint32).reshape(-1, 3)
     return Relational("random_small", values, V, Queries(off, items), 1)
+
+
+# ----------------------------------------------------------------------------
+# sequences (Section 5.1): title-like synthetic text
+# ----------------------------------------------------------------------------
+
+def pack_sequences(seqs) -> tuple:
+    """bytes objects -> (chars uint8 [total], offsets uint64 [n+1])."""
+    lens = np.array([len(x) for x in seqs], dtype=np.uint64)
+    off = np.zeros(len(seqs) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lens, dtype=np.uint64)
+    chars = np.frombuffer(b"".join(bytes(x) for x in seqs), dtype=np.uint8).copy()
+    return chars, off
+
+
+@dataclasses.dataclass
+class SequenceInputs:
+    chars: np.ndarray      # uint8: data sequences back to back
+    offsets: np.ndarray    # uint64 [n+1]
+    qchars: np.ndarray     # uint8: queries back to back
+    qoffsets: np.ndarray   # uint64 [nq+1]
+    sources: np.ndarray    # int64 [nq]: the data sequence each query was made from
+    gram: int              # n of the n-grams
+    K: int                 # candidates taken by match count
+    k: int                 # answers after verification
+
+    @property
+    def n(self) -> int:
+        return self.offsets.size - 1
+
+    @property
+    def nq(self) -> int:
+        return self.qoffsets.size - 1
+
+    def seq(self, i: int) -> bytes:
+        return self.chars[int(self.offsets[i]):int(self.offsets[i + 1])].tobytes()
+
+    def query(self, j: int) -> bytes:
+        return self.qchars[int(self.qoffsets[j]):int(self.qoffsets[j + 1])].tobytes()
+
+
+TEXT_ALPHABET = b"abcdefghijklmnopqrstuvwxyz0123456789"
+
+
+def text_vocabulary(rng, n_words: int, letter_a: float = 0.9):
+    """Pseudo-words: letters drawn from a skewed law (P(letter of rank r) ~
+    (r+1)^-letter_a over a seeded order of the 26 letters, digits rare),
+    lengths 2..12 with the shortest words at the most frequent ranks."""
+    letters = np.frombuffer(TEXT_ALPHABET[:26], np.uint8)[rng.permutation(26)]
+    sym = np.concatenate([letters, np.frombuffer(TEXT_ALPHABET[26:], np.uint8)])
+    w = np.concatenate([np.arange(1, 27, dtype=np.float64) ** (-letter_a),
+                        np.full(10, 0.004)])
+    cdf = np.cumsum(w / w.sum())
+    lens = np.sort(2 + rng.binomial(10, 0.5, size=n_words)).astype(np.int64)
+    off = np.zeros(n_words + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    idx = np.minimum(np.searchsorted(cdf, rng.random(int(off[-1])), side="right"), sym.size - 1)
+    return sym[idx], off
+
+
+def text_corpus(rng, n: int, vocab: int = 30_000, word_a: float = 1.0, wmin: int = 4,
+                wmax: int = 14, chunk: int = 250_000):
+    """n strings of wmin..wmax words (Zipf(word_a) over the vocabulary ranks)
+    joined by single spaces."""
+    vchars, voff = text_vocabulary(rng, vocab)
+    vlen = np.diff(voff)
+    wcdf = np.cumsum(np.arange(1, vocab + 1, dtype=np.float64) ** (-word_a))
+    wcdf /= wcdf[-1]
+    parts, lens_all = [], []
+    for r0 in range(0, n, chunk):
+        c = min(chunk, n - r0)
+        nw = rng.integers(wmin, wmax + 1, size=c)
+        words = np.minimum(np.searchsorted(wcdf, rng.random(int(nw.sum())), side="right"),
+                           vocab - 1)
+        wl = vlen[words] + 1                      # the word and one space after it
+        total = int(wl.sum())
+        rep = np.repeat(np.arange(words.size), wl)
+        wstart = np.cumsum(wl) - wl
+        inword = np.arange(total, dtype=np.int64) - wstart[rep]
+        src = voff[words][rep] + np.minimum(inword, vlen[words][rep] - 1)
+        out = np.where(inword == vlen[words][rep], np.uint8(ord(" ")), vchars[src])
+        # drop the space after the last word of every string
+        seq_end = np.cumsum(np.add.reduceat(wl, np.cumsum(nw) - nw))
+        keep = np.ones(total, dtype=bool)
+        keep[seq_end - 1] = False
+        parts.append(out[keep].astype(np.uint8))
+        lens_all.append(np.add.reduceat(wl, np.cumsum(nw) - nw) - 1)
+    lens = np.concatenate(lens_all).astype(np.uint64)
+    off = np.zeros(n + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lens, dtype=np.uint64)
+    return np.concatenate(parts), off
+
+
+def modified_queries(rng, chars: np.ndarray, offsets: np.ndarray, nq: int, qlen: int,
+                     frac: float, alphabet: bytes = TEXT_ALPHABET + b" "):
+    """nq data strings of exactly qlen characters, each with round(frac * qlen)
+    distinct positions replaced by a different symbol of the alphabet."""
+    lens = np.diff(offsets).astype(np.int64)
+    pool = np.flatnonzero(lens == qlen)
+    if pool.size < nq:
+        raise ValueError(f"only {pool.size} strings of length {qlen}")
+    src = rng.choice(pool, size=nq, replace=False)
+    q = chars[offsets[src].astype(np.int64)[:, None] + np.arange(qlen)].copy()
+    m = int(round(frac * qlen))
+    alpha = np.frombuffer(alphabet, np.uint8)
+    lut = np.full(256, 0, dtype=np.int64)
+    lut[alpha] = np.arange(alpha.size)
+    if m:
+        pos = np.argsort(rng.random((nq, qlen)), axis=1)[:, :m]
+        rows = np.arange(nq)[:, None]
+        old = lut[q[rows, pos]]
+        new = (old + 1 + rng.integers(0, alpha.size - 1, size=old.shape)) % alpha.size
+        q[rows, pos] = alpha[new]
+    qoff = np.arange(nq + 1, dtype=np.uint64) * np.uint64(qlen)
+    return q.reshape(-1).astype(np.uint8), qoff, src.astype(np.int64)
+
+
+def sequence(n: int = 5_000_000, nq: int = 1024, qlen: int = 40, frac: float = 0.2,
+             gram: int = 3, K: int = 32, k: int = 1, salt: int = 0) -> SequenceInputs:
+    """Sequence search under edit distance (Section 5.1) on title-like text;
+    stands in for the DBLP titles of Section 6.1.1."""
+    ro, rq, _ = rng_streams(CONFIG_IDS["sequence"], salt)
+    chars, off = text_corpus(ro, n)
+    qc, qo, src = modified_queries(rq, chars, off, nq, qlen, frac)
+    return SequenceInputs(chars, off, qc, qo, src, gram, K, k)
+
+
+def random_sequences(rng, n: int, alphabet: bytes, lmin: int, lmax: int):
+    """Adversarial strings: i.i.d. symbols of a small alphabet (many repeated
+    n-grams), lengths uniform in [lmin, lmax] (0 allowed)."""
+    lens = rng.integers(lmin, lmax + 1, size=n)
+    alpha = np.frombuffer(alphabet, np.uint8)
+    chars = alpha[rng.integers(0, alpha.size, size=int(lens.sum()))]
+    off = np.zeros(n + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(lens, dtype=np.uint64)
+    return chars.astype(np.uint8), off
