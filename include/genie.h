@@ -60,6 +60,7 @@ extern "C" {
 #define GENIE_STATUS_BAD_DIM 1u       /* an item named dim >= n_dims (treated as empty) */
 #define GENIE_STATUS_TOO_MANY_ITEMS 2u /* a query had more items than max_items (row padded) */
 #define GENIE_STATUS_BAD_OFFSETS 4u    /* a query's offsets were invalid (row padded) */
+#define GENIE_STATUS_RANGE_ON_SET 8u   /* an item on a keyword-set index spanned several keywords (treated as empty) */
 
 typedef struct genie_index genie_index; /* opaque, owned by the library */
 
@@ -425,6 +426,138 @@ int genie_match_count_async(const genie_index *ix, const uint64_t *d_q_offsets,
 int genie_lsh_signatures(const float *d_points, uint64_t n, uint32_t dim, const float *d_a,
                          const float *d_b, float w, uint32_t m, const uint64_t *d_rehash,
                          uint32_t log2_buckets, uint32_t *d_out_sig, void *stream);
+
+/*
+ * Index over keyword sets (the Shotgun-and-Assembly scheme of Section 2.2
+ * and Section 5: an object is a set of keywords, such as the words of a
+ * short document, Section 5.2, or the ordered n-grams of a sequence,
+ * Section 5.1.1).  Object o holds the keywords keys[obj_offsets[o] ..
+ * obj_offsets[o+1]), each below n_keys and each at most once per object.
+ *   obj_offsets: host, n_objects + 1 uint64, non-decreasing.
+ *   keys:        host, obj_offsets[n_objects] - obj_offsets[0] uint32
+ *                (may be NULL when that is 0).
+ *   n_objects: 1 .. 2^32 - 2; n_keys: 1 .. 2^32 - 2; tile_log2: 15 or 16.
+ * The index has n_dims = 1 and n_buckets = n_keys: the query item
+ * (0, key, key) is the list of one keyword.  Every item on this index must
+ * name one keyword (lo == hi) or be empty, which keeps every count at most
+ * the number of items; a range item is an error of genie_search and is
+ * treated as empty by the asynchronous searches, which then raise
+ * GENIE_STATUS_RANGE_ON_SET.  Device layout and errors as
+ * genie_build_index_tiled (GENIE_EINVAL also for a key >= n_keys or
+ * decreasing offsets).
+ */
+int genie_build_index_sets(const uint64_t *obj_offsets, const uint32_t *keys, uint64_t n_objects,
+                           uint32_t n_keys, uint32_t tile_log2, genie_index **out);
+
+/*
+ * Similarity search on sequences under edit distance (Section 5.1).
+ * A sequence is a string of bytes; the edit distance counts unit-cost
+ * single-byte insertions, deletions and substitutions.
+ */
+typedef struct genie_seq_index genie_seq_index; /* opaque, owned by the library */
+
+typedef struct {
+    uint64_t n_sequences;
+    uint64_t n_chars;          /* bytes of all sequences */
+    uint64_t n_windows;        /* ordered n-grams of all sequences (postings) */
+    uint32_t gram;             /* n of the n-grams */
+    uint32_t alphabet;         /* distinct byte values in the data */
+    uint32_t n_grams;          /* distinct n-grams in the data */
+    uint32_t n_keys;           /* distinct ordered n-grams (keywords of the index) */
+    uint32_t max_occurrences;  /* most occurrences of one n-gram in one sequence */
+    uint32_t n_tiles;
+    uint64_t device_bytes;     /* index, sequences and n-gram table on the device */
+} genie_seq_info;
+
+/*
+ * Shotgun (Section 5.1.1): decompose every sequence into its ordered
+ * n-grams G(S) (Example 5.1) and build the match-count index over them,
+ * keeping the sequences on the device for verification.
+ *   chars:   host, offsets[n_sequences] bytes: the sequences back to back.
+ *   offsets: host, n_sequences + 1 uint64, offsets[0] = 0, non-decreasing;
+ *            sequence i is chars[offsets[i] .. offsets[i+1]).
+ *   gram:    n, 1..8.  alphabet^gram (alphabet = distinct byte values of
+ *            the data) must be at most 2^24 (GENIE_ERANGE otherwise).
+ *   tile_log2: 15 or 16 (tiles of the match-count index).
+ * Errors: GENIE_EINVAL, GENIE_ERANGE, GENIE_ENOMEM, GENIE_EDEVICE.
+ */
+int genie_seq_build(const uint8_t *chars, const uint64_t *offsets, uint64_t n_sequences,
+                    uint32_t gram, uint32_t tile_log2, genie_seq_index **out);
+
+/* Free a sequence index and its device memory.  NULL is ignored. */
+void genie_seq_free(genie_seq_index *sx);
+
+/* Describe a sequence index.  Errors: GENIE_EINVAL. */
+int genie_seq_info_get(const genie_seq_index *sx, genie_seq_info *out);
+
+/* The match-count index of a sequence index (owned by it; NULL for NULL). */
+genie_index *genie_seq_match_index(genie_seq_index *sx);
+
+/*
+ * Query decomposition (Section 5.1.2): the items of every query's ordered
+ * n-grams on the index of genie_seq_match_index.  Item r of query q is
+ * written at d_items[d_qoffsets[q] + r] (one item per query byte): window r
+ * gives (0, key, key) for the keyword of its ordered n-gram, or the empty
+ * item (0, 1, 0) when no data sequence holds that ordered n-gram; the last
+ * gram - 1 bytes of a query start no window and give empty items.  So the
+ * query offsets are also the item offsets, and the match count of a
+ * sequence S is |G(S) and G(Q)| (Lemma 5.1).
+ *   d_qchars: device, n_qchars bytes; d_qoffsets: device, n_queries + 1,
+ *   non-decreasing, d_qoffsets[n_queries] <= n_qchars; d_items: device,
+ *   n_qchars items.  A query whose offsets are invalid gets no items; one
+ *   longer than GENIE_MAX_ITEMS gets empty items (the search pads its row).
+ * Errors: GENIE_EINVAL (null pointer); launch errors GENIE_EDEVICE.
+ */
+int genie_seq_decompose_async(const genie_seq_index *sx, const uint8_t *d_qchars,
+                              const uint64_t *d_qoffsets, uint64_t n_qchars, uint32_t n_queries,
+                              genie_item *d_items, void *stream);
+
+/*
+ * Verification (Algorithm 2, Section 5.1.2) of K candidates per query,
+ * given in count order (genie_search_async's output on the match index).
+ * Answer: the k candidates of smallest edit distance to the query, ties to
+ * the earlier candidate (Algorithm 2 with k = 1; its filtering bound and
+ * length filter skip only candidates that cannot change this answer).
+ *   d_cand_ids, d_cand_counts: device, n_queries * K; ids >= n_sequences
+ *     are empty slots (distance UINT32_MAX).
+ *   max_qlen: at least every query's length, at most GENIE_MAX_ITEMS.
+ *   d_out_ids, d_out_dist: device, n_queries * k, best first; slots past
+ *     the valid candidates hold UINT32_MAX.
+ *   d_out_cert: device, n_queries: 1 if Theorem 5.2 certifies the answer as
+ *     the true k nearest sequences of the whole data set (c_K <
+ *     |Q| - n + 1 - tau_k' n, c_K the K-th candidate's count, tau_k' the
+ *     k-th answer's distance), or if K >= n_sequences; else 0.
+ * A query with invalid offsets or longer than max_qlen's bit-vector width
+ * gets UINT32_MAX answers and certificate 0.
+ * Errors: GENIE_EINVAL (null pointer; need 1 <= k <= K <= GENIE_MAX_K),
+ * GENIE_ERANGE (max_qlen), GENIE_EDEVICE.
+ */
+int genie_seq_verify_async(const genie_seq_index *sx, const uint8_t *d_qchars,
+                           const uint64_t *d_qoffsets, uint64_t n_qchars, uint32_t n_queries,
+                           uint32_t max_qlen, const uint32_t *d_cand_ids,
+                           const uint32_t *d_cand_counts, uint32_t K, uint32_t k,
+                           uint32_t *d_out_ids, uint32_t *d_out_dist, uint32_t *d_out_cert,
+                           void *stream);
+
+/* Workspace bytes for genie_seq_search_async (0 for a NULL index). */
+size_t genie_seq_workspace_size(const genie_seq_index *sx, uint32_t n_queries, uint64_t n_qchars,
+                                uint32_t K);
+
+/*
+ * Sequence search (Section 5.1): decomposition, top-K match-count search
+ * (c-PQ, as genie_search_async) and verification, on `stream`, writing
+ * what genie_seq_verify_async writes.  The workspace (device, 256-byte
+ * aligned, genie_seq_workspace_size bytes) starts with the search
+ * workspace, so its status word and statistics are read as for
+ * genie_search_async; it also holds the items and the K candidates.
+ * Arguments and errors as genie_seq_decompose_async and
+ * genie_seq_verify_async.
+ */
+int genie_seq_search_async(const genie_seq_index *sx, const uint8_t *d_qchars,
+                           const uint64_t *d_qoffsets, uint64_t n_qchars, uint32_t n_queries,
+                           uint32_t max_qlen, uint32_t K, uint32_t k, uint32_t *d_out_ids,
+                           uint32_t *d_out_dist, uint32_t *d_out_cert, void *d_workspace,
+                           size_t workspace_bytes, void *stream);
 
 /*
  * Per-kernel timing for measurement.  While enabled, every search call

@@ -32,6 +32,7 @@ GENIE_TILE_OBJECTS = 65535
 STATUS_BAD_DIM = 1
 STATUS_TOO_MANY_ITEMS = 2
 STATUS_BAD_OFFSETS = 4
+STATUS_RANGE_ON_SET = 8
 
 EXPORTED = (
     "genie_build_index", "genie_build_index_tiled", "genie_free_index", "genie_index_info_get",
@@ -44,6 +45,9 @@ EXPORTED = (
     "genie_index_set_scan_schedule", "genie_search_rows_async", "genie_parts_build",
     "genie_parts_free", "genie_parts_info_get", "genie_parts_workspace_size",
     "genie_parts_search_async", "genie_search_spq_async", "genie_rbh_signatures",
+    "genie_build_index_sets", "genie_seq_build", "genie_seq_free", "genie_seq_info_get",
+    "genie_seq_match_index", "genie_seq_decompose_async", "genie_seq_verify_async",
+    "genie_seq_workspace_size", "genie_seq_search_async",
 )
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
@@ -64,6 +68,14 @@ class _PartsInfo(ctypes.Structure):
     _fields_ = [("n_objects", ctypes.c_uint64), ("n_parts", ctypes.c_uint32),
                 ("tiles_total", ctypes.c_uint32), ("part_objects", ctypes.c_uint64),
                 ("host_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64)]
+
+
+class _SeqInfo(ctypes.Structure):
+    _fields_ = [("n_sequences", ctypes.c_uint64), ("n_chars", ctypes.c_uint64),
+                ("n_windows", ctypes.c_uint64), ("gram", ctypes.c_uint32),
+                ("alphabet", ctypes.c_uint32), ("n_grams", ctypes.c_uint32),
+                ("n_keys", ctypes.c_uint32), ("max_occurrences", ctypes.c_uint32),
+                ("n_tiles", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
 
 
 class _IndexInfo(ctypes.Structure):
@@ -147,6 +159,26 @@ def load() -> ctypes.CDLL:
     lib.genie_index_set_scan_shape.restype = ctypes.c_int
     lib.genie_index_set_scan_schedule.argtypes = [vp, u32]
     lib.genie_index_set_scan_schedule.restype = ctypes.c_int
+    lib.genie_build_index_sets.argtypes = [vp, vp, u64, u32, u32, ctypes.POINTER(vp)]
+    lib.genie_build_index_sets.restype = ctypes.c_int
+    lib.genie_seq_build.argtypes = [vp, vp, u64, u32, u32, ctypes.POINTER(vp)]
+    lib.genie_seq_build.restype = ctypes.c_int
+    lib.genie_seq_free.argtypes = [vp]
+    lib.genie_seq_free.restype = None
+    lib.genie_seq_info_get.argtypes = [vp, ctypes.POINTER(_SeqInfo)]
+    lib.genie_seq_info_get.restype = ctypes.c_int
+    lib.genie_seq_match_index.argtypes = [vp]
+    lib.genie_seq_match_index.restype = vp
+    lib.genie_seq_decompose_async.argtypes = [vp, vp, vp, u64, u32, vp, vp]
+    lib.genie_seq_decompose_async.restype = ctypes.c_int
+    lib.genie_seq_verify_async.argtypes = [vp, vp, vp, u64, u32, u32, vp, vp, u32, u32, vp, vp,
+                                           vp, vp]
+    lib.genie_seq_verify_async.restype = ctypes.c_int
+    lib.genie_seq_workspace_size.argtypes = [vp, u32, u64, u32]
+    lib.genie_seq_workspace_size.restype = sz
+    lib.genie_seq_search_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, u32, vp, vp, vp, vp,
+                                           sz, vp]
+    lib.genie_seq_search_async.restype = ctypes.c_int
     lib.genie_last_error.argtypes = []
     lib.genie_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -230,6 +262,165 @@ class Index:
             self.free()
         except Exception:
             pass
+
+
+class _BorrowedIndex(Index):
+    """An index owned by another object (e.g. a sequence index's match index)."""
+
+    def __init__(self, handle, owner):
+        self._h = ctypes.c_void_p(handle)
+        self._owner = owner
+        self.refresh_info()
+
+    def free(self):
+        self._h = None
+
+
+def genie_build_index_sets(obj_offsets: np.ndarray, keys: np.ndarray, n_keys: int,
+                           tile_log2: int = 16) -> Index:
+    """Index over keyword sets: object o holds keys[obj_offsets[o] ..
+    obj_offsets[o+1]) (Sections 2.2 and 5); query items name one keyword each."""
+    obj_offsets = np.ascontiguousarray(obj_offsets, dtype=np.uint64)
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    ix = Index.__new__(Index)
+    h = ctypes.c_void_p()
+    _check(load().genie_build_index_sets(_np_ptr(obj_offsets),
+                                         _np_ptr(keys) if keys.size else None,
+                                         obj_offsets.size - 1, int(n_keys), int(tile_log2),
+                                         ctypes.byref(h)))
+    ix._h = h
+    ix.refresh_info()
+    return ix
+
+
+class SeqIndex:
+    """genie_seq_build: sequences decomposed into ordered n-grams and indexed
+    for match-count search, kept on the device for verification (Section 5.1)."""
+
+    def __init__(self, chars: np.ndarray, offsets: np.ndarray, gram: int = 3,
+                 tile_log2: int = 16):
+        chars = np.ascontiguousarray(chars, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        h = ctypes.c_void_p()
+        _check(load().genie_seq_build(_np_ptr(chars) if chars.size else None, _np_ptr(offsets),
+                                      offsets.size - 1, int(gram), int(tile_log2),
+                                      ctypes.byref(h)))
+        self._h = h
+        info = _SeqInfo()
+        _check(load().genie_seq_info_get(self._h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _SeqInfo._fields_}
+        self.match_index = _BorrowedIndex(load().genie_seq_match_index(self._h), self)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise GenieError(GENIE_EINVAL, "sequence index is freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            self.match_index.free()
+            load().genie_seq_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def workspace(self, n_queries: int, n_qchars: int, K: int, device="cuda"):
+        import torch
+        nbytes = load().genie_seq_workspace_size(self.handle, int(n_queries), int(n_qchars),
+                                                 int(K))
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def genie_seq_build(chars: np.ndarray, offsets: np.ndarray, gram: int = 3,
+                    tile_log2: int = 16) -> SeqIndex:
+    return SeqIndex(chars, offsets, gram, tile_log2)
+
+
+def genie_seq_free(sx: SeqIndex):
+    sx.free()
+
+
+def genie_seq_info_get(sx: SeqIndex) -> dict:
+    return dict(sx.info)
+
+
+def genie_seq_match_index(sx: SeqIndex) -> Index:
+    return sx.match_index
+
+
+def genie_seq_workspace_size(sx: SeqIndex, n_queries: int, n_qchars: int, K: int) -> int:
+    return int(load().genie_seq_workspace_size(sx.handle, int(n_queries), int(n_qchars), int(K)))
+
+
+def genie_seq_decompose_async(sx: SeqIndex, d_qchars, d_qoffsets, out_items=None, stream=None):
+    """Items of the queries' ordered n-grams, one per query byte (Section 5.1.2)."""
+    import torch
+    nq = d_qoffsets.numel() - 1
+    if out_items is None:
+        out_items = torch.empty((max(d_qchars.numel(), 1), 3), dtype=torch.int32,
+                                device=d_qoffsets.device)
+    if nq > 0:
+        _check(load().genie_seq_decompose_async(sx.handle, _dev_ptr(d_qchars),
+                                                _dev_ptr(d_qoffsets), d_qchars.numel(), nq,
+                                                _dev_ptr(out_items), _stream_handle(stream)))
+    return out_items
+
+
+def _seq_outputs(nq, k, dev, out_ids, out_dist, out_cert):
+    import torch
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if out_dist is None:
+        out_dist = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if out_cert is None:
+        out_cert = torch.empty((max(nq, 1),), dtype=torch.int32, device=dev)
+    return out_ids, out_dist, out_cert
+
+
+def genie_seq_verify_async(sx: SeqIndex, d_qchars, d_qoffsets, max_qlen: int, d_cand_ids,
+                           d_cand_counts, k: int, out_ids=None, out_dist=None, out_cert=None,
+                           stream=None):
+    """Algorithm 2 over K candidates per query ([nq, K] in count order) and
+    the certificate of Theorem 5.2; returns (ids, dist, cert)."""
+    nq = d_qoffsets.numel() - 1
+    K = d_cand_ids.shape[1]
+    if (d_cand_ids.dim() != 2 or tuple(d_cand_counts.shape) != tuple(d_cand_ids.shape)
+            or d_cand_ids.shape[0] < nq):
+        raise ValueError("candidates must be [n_queries, K] ids and counts")
+    out_ids, out_dist, out_cert = _seq_outputs(nq, k, d_qoffsets.device, out_ids, out_dist,
+                                               out_cert)
+    if nq > 0:
+        _check(load().genie_seq_verify_async(sx.handle, _dev_ptr(d_qchars), _dev_ptr(d_qoffsets),
+                                             d_qchars.numel(), nq, int(max_qlen),
+                                             _dev_ptr(d_cand_ids), _dev_ptr(d_cand_counts),
+                                             int(K), int(k), _dev_ptr(out_ids),
+                                             _dev_ptr(out_dist), _dev_ptr(out_cert),
+                                             _stream_handle(stream)))
+    return out_ids, out_dist, out_cert
+
+
+def genie_seq_search_async(sx: SeqIndex, d_qchars, d_qoffsets, max_qlen: int, K: int, k: int,
+                           out_ids=None, out_dist=None, out_cert=None, workspace=None,
+                           stream=None):
+    """Decomposition, top-K match-count search and verification (Section 5.1);
+    returns (ids, dist, cert, workspace)."""
+    nq = d_qoffsets.numel() - 1
+    dev = d_qoffsets.device
+    out_ids, out_dist, out_cert = _seq_outputs(nq, k, dev, out_ids, out_dist, out_cert)
+    if workspace is None:
+        workspace = sx.workspace(max(nq, 0), d_qchars.numel(), K, dev)
+    if nq > 0:
+        _check(load().genie_seq_search_async(sx.handle, _dev_ptr(d_qchars), _dev_ptr(d_qoffsets),
+                                             d_qchars.numel(), nq, int(max_qlen), int(K), int(k),
+                                             _dev_ptr(out_ids), _dev_ptr(out_dist),
+                                             _dev_ptr(out_cert), _dev_ptr(workspace),
+                                             workspace.numel(), _stream_handle(stream)))
+    return out_ids, out_dist, out_cert, workspace
 
 
 class PartsIndex:

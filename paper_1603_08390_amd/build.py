@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/api.cpp", "csrc/search.hip", "csrc/lsh.hip", "csrc/gate.hip", "csrc/timing.cpp",
-           "csrc/parts.cpp"]
+           "csrc/parts.cpp", "csrc/sequence.hip"]
 LIB = os.path.join(HERE, "libgenie.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

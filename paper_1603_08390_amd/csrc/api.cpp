@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -104,29 +105,19 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
 
 namespace genie {
 
-int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
-                     uint32_t tile_log2, HostIndex *h) {
-    if (!values) {
-        set_error("null pointer");
-        return GENIE_EINVAL;
-    }
+// Shared by both index forms: keys_of(o, emit) calls emit(key) once for
+// every keyword of object o and returns false if a keyword is out of range.
+template <class KeysOf>
+static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nkeys,
+                                 uint64_t npost, uint32_t tile_log2, const KeysOf &keys_of,
+                                 HostIndex *h) {
     if (tile_log2 != 15 && tile_log2 != 16) {
         set_error("tile_log2 must be 15 or 16 (got %u)", tile_log2);
         return GENIE_EINVAL;
     }
     const uint32_t kTile = tile_objects_of(tile_log2);
     const uint16_t kSentinel = (uint16_t)kTile;
-    if (n == 0 || n >= 0xFFFFFFFFull || d == 0 || V == 0 || (uint64_t)d * V >= 0xFFFFFFFFull) {
-        set_error("bad sizes n=%llu d=%u V=%u", (unsigned long long)n, d, V);
-        return GENIE_EINVAL;
-    }
     const uint32_t T = (uint32_t)((n + kTile - 1) / kTile);
-    const uint64_t nkeys = (uint64_t)d * V;
-    const uint64_t npost = n * d;
-    if ((uint64_t)kTile * d + nkeys >= 0xFFFFFFFFull) {
-        set_error("n_dims * n_buckets too large for 32-bit tile offsets");
-        return GENIE_EINVAL;
-    }
 
     // Per tile: run length of every keyword (counting sort), each run padded
     // to an even number of elements with the sentinel id kSentinel so that
@@ -138,7 +129,7 @@ int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
     std::vector<uint64_t> tile_size(T);
     std::vector<uint64_t> &tile_base = h->tile_base;
     tile_base.assign(T + 1, 0);
-    std::atomic<int> bad{0};
+    std::atomic<int> bad{0}, overflow{0};
     std::atomic<uint32_t> next{0};
     auto count_tiles = [&]() {
         for (;;) {
@@ -149,24 +140,23 @@ int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
             uint32_t *row = &toff[(uint64_t)t * (nkeys + 1)];
             uint32_t *prow = &tpad[(uint64_t)t * (nkeys + 1)];
             for (uint64_t o = o0; o < o1; o++)
-                for (uint32_t j = 0; j < d; j++) {
-                    uint32_t v = values[o * d + j];
-                    if (v >= V) {
-                        bad.store(1);
-                        return;
-                    }
-                    row[(uint64_t)j * V + v + 1]++;
+                if (!keys_of(o, [&](uint64_t key) { row[key + 1]++; })) {
+                    bad.store(1);
+                    return;
                 }
-            uint32_t off = 0, pads = 0;
+            uint64_t off = 0;
+            uint32_t pads = 0;
             row[0] = 0;
             prow[0] = 0;
             for (uint64_t key = 0; key < nkeys; key++) {
                 uint32_t len = row[key + 1];
                 off += len + (len & 1u);
                 pads += len & 1u;
-                row[key + 1] = off;
+                row[key + 1] = (uint32_t)off;
                 prow[key + 1] = pads;
             }
+            if (off + 2 * kSentinelDwords >= 0xFFFFFFFFull)
+                overflow.store(1);
             tile_size[t] = off + 2 * kSentinelDwords;   // trailing all-sentinel dwords
         }
     };
@@ -180,7 +170,12 @@ int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
             th.join();
     }
     if (bad.load()) {
-        set_error("a value is >= n_buckets (%u)", V);
+        set_error("a keyword is out of range (n_buckets %u, keywords %llu)", V,
+                  (unsigned long long)nkeys);
+        return GENIE_EINVAL;
+    }
+    if (overflow.load()) {
+        set_error("a tile holds too many postings for 32-bit tile offsets");
         return GENIE_EINVAL;
     }
     tile_base[0] = 0;
@@ -212,10 +207,7 @@ int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
             uint16_t *dst = &post[tile_base[t]];
             // objects in ascending id order: every run ascends
             for (uint64_t o = o0; o < o1; o++)
-                for (uint32_t j = 0; j < d; j++) {
-                    uint64_t key = (uint64_t)j * V + values[o * d + j];
-                    dst[fill[key]++] = (uint16_t)(o - o0);
-                }
+                keys_of(o, [&](uint64_t key) { dst[fill[key]++] = (uint16_t)(o - o0); });
         }
     };
     {
@@ -235,6 +227,103 @@ int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
     return GENIE_OK;
 }
 
+int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
+                     uint32_t tile_log2, HostIndex *h) {
+    if (!values) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (n == 0 || n >= 0xFFFFFFFFull || d == 0 || V == 0 || (uint64_t)d * V >= 0xFFFFFFFFull) {
+        set_error("bad sizes n=%llu d=%u V=%u", (unsigned long long)n, d, V);
+        return GENIE_EINVAL;
+    }
+    const uint64_t nkeys = (uint64_t)d * V;
+    auto keys_of = [&](uint64_t o, const auto &emit) {
+        for (uint32_t j = 0; j < d; j++) {
+            const uint32_t v = values[o * d + j];
+            if (v >= V)
+                return false;
+            emit((uint64_t)j * V + v);
+        }
+        return true;
+    };
+    return build_host_index_impl(n, d, V, nkeys, n * d, tile_log2, keys_of, h);
+}
+
+int build_host_index_sets(const uint64_t *obj_offsets, const uint32_t *keys, uint64_t n,
+                          uint32_t n_keys, uint32_t tile_log2, HostIndex *h) {
+    if (!obj_offsets || (!keys && n && obj_offsets[n] != obj_offsets[0])) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
+    }
+    if (n == 0 || n >= 0xFFFFFFFFull || n_keys == 0 || n_keys == 0xFFFFFFFFu) {
+        set_error("bad sizes n=%llu n_keys=%u", (unsigned long long)n, n_keys);
+        return GENIE_EINVAL;
+    }
+    for (uint64_t o = 0; o < n; o++)
+        if (obj_offsets[o + 1] < obj_offsets[o]) {
+            set_error("object offsets decrease at object %llu", (unsigned long long)o);
+            return GENIE_EINVAL;
+        }
+    auto keys_of = [&](uint64_t o, const auto &emit) {
+        for (uint64_t i = obj_offsets[o]; i < obj_offsets[o + 1]; i++) {
+            if (keys[i] >= n_keys)
+                return false;
+            emit((uint64_t)keys[i]);
+        }
+        return true;
+    };
+    int rc = build_host_index_impl(n, 1, n_keys, n_keys, obj_offsets[n] - obj_offsets[0],
+                                   tile_log2, keys_of, h);
+    if (rc == GENIE_OK)
+        h->key_sets = true;
+    return rc;
+}
+
+}  // namespace genie
+
+namespace genie {
+
+int upload_host_index(const HostIndex &h, genie_index **out) {
+    const uint32_t T = h.n_tiles;
+    genie_index *ix = new (std::nothrow) genie_index;
+    if (!ix) {
+        set_error("host allocation failed");
+        return GENIE_ENOMEM;
+    }
+    ix->n = h.n;
+    ix->d = h.d;
+    ix->V = h.V;
+    ix->n_tiles = T;
+    ix->tile_log2 = h.tile_log2;
+    ix->tile_objects = tile_objects_of(h.tile_log2);
+    ix->nkeys = h.nkeys;
+    ix->n_postings = h.n_postings;
+    ix->stored_postings = h.tile_base[T];
+    ix->key_sets = h.key_sets;
+    hipError_t e = hipGetDevice(&ix->device);
+    size_t bp = h.post.size() * sizeof(uint16_t), bb = h.tile_base.size() * sizeof(uint64_t),
+           bt = h.toff.size() * sizeof(uint32_t), bk = h.kcum.size() * sizeof(uint64_t);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->post, bp);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->tile_base, bb);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->toff, bt);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->tpad, bt);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->kcum, bk);
+    if (e == hipSuccess) e = hipMemcpy(ix->kcum, h.kcum.data(), bk, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ix->post, h.post.data(), bp, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ix->tile_base, h.tile_base.data(), bb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ix->toff, h.toff.data(), bt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ix->tpad, h.tpad.data(), bt, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        int rc = hip_fail(e, "index upload");
+        genie_free_index(ix);
+        return rc;
+    }
+    ix->device_bytes = bp + bb + 2 * bt + bk;
+    *out = ix;
+    return GENIE_OK;
+}
+
 }  // namespace genie
 
 extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
@@ -245,53 +334,33 @@ extern "C" int genie_build_index_tiled(const uint32_t *values, uint64_t n, uint3
         return GENIE_EINVAL;
     }
     *out = nullptr;
-    HostIndex h;
-    int brc = build_host_index(values, n, d, V, tile_log2, &h);
-    if (brc)
-        return brc;
-    const uint32_t kTile = tile_objects_of(tile_log2);
-    const uint32_t T = h.n_tiles;
-    const uint64_t nkeys = h.nkeys, npost = h.n_postings;
-    const uint64_t stored = h.tile_base[T];
-    const std::vector<uint16_t> &post = h.post;
-    const std::vector<uint64_t> &tile_base = h.tile_base, &kcum = h.kcum;
-    const std::vector<uint32_t> &toff = h.toff, &tpad = h.tpad;
-    genie_index *ix = new (std::nothrow) genie_index;
-    if (!ix) {
-        set_error("host allocation failed");
+    try {
+        HostIndex h;
+        int rc = build_host_index(values, n, d, V, tile_log2, &h);
+        return rc ? rc : upload_host_index(h, out);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed while building the index");
         return GENIE_ENOMEM;
     }
-    ix->n = n;
-    ix->d = d;
-    ix->V = V;
-    ix->n_tiles = T;
-    ix->tile_log2 = tile_log2;
-    ix->tile_objects = kTile;
-    ix->nkeys = nkeys;
-    ix->n_postings = npost;
-    ix->stored_postings = stored;
-    hipError_t e = hipGetDevice(&ix->device);
-    size_t bp = post.size() * sizeof(uint16_t), bb = tile_base.size() * sizeof(uint64_t),
-           bt = toff.size() * sizeof(uint32_t);
-    if (e == hipSuccess) e = hipMalloc((void **)&ix->post, bp);
-    if (e == hipSuccess) e = hipMalloc((void **)&ix->tile_base, bb);
-    if (e == hipSuccess) e = hipMalloc((void **)&ix->toff, bt);
-    if (e == hipSuccess) e = hipMalloc((void **)&ix->tpad, bt);
-    if (e == hipSuccess) e = hipMalloc((void **)&ix->kcum, kcum.size() * sizeof(uint64_t));
-    if (e == hipSuccess)
-        e = hipMemcpy(ix->kcum, kcum.data(), kcum.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ix->post, post.data(), bp, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ix->tile_base, tile_base.data(), bb, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ix->toff, toff.data(), bt, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ix->tpad, tpad.data(), bt, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        int rc = hip_fail(e, "index upload");
-        genie_free_index(ix);
-        return rc;
+}
+
+extern "C" int genie_build_index_sets(const uint64_t *obj_offsets, const uint32_t *keys,
+                                      uint64_t n, uint32_t n_keys, uint32_t tile_log2,
+                                      genie_index **out) {
+    clear_error();
+    if (!obj_offsets || !out) {
+        set_error("null pointer");
+        return GENIE_EINVAL;
     }
-    ix->device_bytes = bp + bb + 2 * bt + kcum.size() * sizeof(uint64_t);
-    *out = ix;
-    return GENIE_OK;
+    *out = nullptr;
+    try {
+        HostIndex h;
+        int rc = build_host_index_sets(obj_offsets, keys, n, n_keys, tile_log2, &h);
+        return rc ? rc : upload_host_index(h, out);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed while building the index");
+        return GENIE_ENOMEM;
+    }
 }
 
 extern "C" void genie_free_index(genie_index *ix) {
@@ -565,12 +634,18 @@ extern "C" int genie_search(const genie_index *ix, const uint64_t *q_offsets,
         set_error("null items");
         return GENIE_EINVAL;
     }
-    for (uint64_t i = 0; i < n_items; i++)
+    for (uint64_t i = 0; i < n_items; i++) {
         if (items[i].dim >= ix->d) {
             set_error("item %llu names dim %u >= n_dims %u", (unsigned long long)i, items[i].dim,
                       ix->d);
             return GENIE_EINVAL;
         }
+        if (ix->key_sets && items[i].lo < std::min(items[i].hi, ix->V - 1)) {
+            set_error("item %llu spans keywords %u..%u of a keyword-set index (one keyword per "
+                      "item)", (unsigned long long)i, items[i].lo, items[i].hi);
+            return GENIE_EINVAL;
+        }
+    }
     SearchShape shape;
     rc = search_shape(max_items, k, ix->scan_threads, ix->tile_log2, &shape);
     if (rc)

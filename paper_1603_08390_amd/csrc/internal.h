@@ -53,6 +53,7 @@ struct genie_index {
     int scan_threads = kScanThreadsDefault;   // launch shape of the scan kernel
     int scan_unroll = kScanUnrollDefault;
     int scan_persistent = 0;                  // 1: persistent workgroups over a pair queue
+    bool key_sets = false;                    // built from keyword sets: d = 1, V = keywords
 };
 
 namespace genie {
@@ -64,9 +65,16 @@ struct HostIndex {
     std::vector<uint16_t> post;
     std::vector<uint64_t> tile_base, kcum;
     std::vector<uint32_t> toff, tpad;
+    bool key_sets = false;
 };
 int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
                      uint32_t tile_log2, HostIndex *h);
+// Objects given as keyword sets: object o holds keys[obj_offsets[o] ..
+// obj_offsets[o+1]), each below n_keys.  The index has d = 1 and V = n_keys,
+// so the item (0, key, key) is the list of one keyword.
+int build_host_index_sets(const uint64_t *obj_offsets, const uint32_t *keys, uint64_t n,
+                          uint32_t n_keys, uint32_t tile_log2, HostIndex *h);
+int upload_host_index(const HostIndex &h, genie_index **out);
 
 void set_error(const char *fmt, ...);
 void clear_error();

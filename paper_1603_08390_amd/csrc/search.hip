@@ -50,6 +50,7 @@ struct ScanParams {
     uint64_t id_base;
     uint32_t tile_off, tiles_total;
     uint32_t spq;           // 1: GEN-SPQ ablation (count everything, then select)
+    uint32_t key_sets;      // 1: keyword-set index, every item names one keyword
 };
 
 struct MergeParams {
@@ -281,7 +282,12 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                 atomicOr(p.status, GENIE_STATUS_BAD_DIM);
         } else {
             hi = min(hi, p.V - 1);
-            if (lo <= hi) {
+            if (p.key_sets && lo < hi) {
+                // an object holds a keyword at most once, so one keyword per
+                // item keeps every count at most the number of items
+                if (t == 0)
+                    atomicOr(p.status, GENIE_STATUS_RANGE_ON_SET);
+            } else if (lo <= hi) {
                 const uint64_t key = (uint64_t)dim * p.V;
                 b = trow[key + lo];
                 e = trow[key + hi + 1];
@@ -923,6 +929,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.nkeys1 = ix->nkeys + 1;
     sp.d = ix->d;
     sp.V = ix->V;
+    sp.key_sets = ix->key_sets ? 1u : 0u;
     sp.n_tiles = ix->n_tiles;
     sp.id_base = 0;
     sp.tile_off = 0;
