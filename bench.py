@@ -83,7 +83,9 @@ METRICS = {
                "included; learned-gate vs plain c-PQ",
     "serving": "queries/sec and p50/p99 latency of the request loop, relational + tau-ANN mix, "
                "k in {10,100,1000}; learned gate off and on",
-    "sequence": "queries/sec, sequence search under edit distance, 5M strings, K=32, k=1",
+    "sequence": "queries/sec, sequence search under edit distance, 5M strings, query length 40 "
+                "with 20% modified, 3-grams, K=32 candidates, k=1; decomposition, verification "
+                "and certificate included; learned-gate vs plain c-PQ",
 }
 HBM_PEAK_GBS = 8000.0
 # Conflict-free LDS atomic add (with return), lane-consecutive addresses,
@@ -209,6 +211,8 @@ class SearchBench:
         self.plain_shape = None
         self.gate_shape = None
         self.spq = True
+        # optional step after the search, on the same stream: post(st, ids, counts)
+        self.post = None
         self.set_gate_index(ix)
 
     def set_gate_index(self, gix):
@@ -220,6 +224,8 @@ class SearchBench:
         off, items = self.prep(st)
         self.genie.genie_search_async(self.ix, off, items, self.k, self.max_items, self.ids,
                                       self.cts, self.ws, st)
+        if self.post:
+            self.post(st, self.ids, self.cts)
 
     def gated_step(self):
         g, m = self.genie, self.model
@@ -229,6 +235,8 @@ class SearchBench:
         m.predict(self.feats, out=self.pred, stream=st)
         g.genie_search_gated_async(self.gix, off, items, self.k, self.max_items, self.pred,
                                    m.delta, self.gids, self.gcts, self.gws, st)
+        if self.post:
+            self.post(st, self.gids, self.gcts)
 
     def graphed(self, step):
         """Record one step in a HIP graph (after an eager run on the capture
@@ -303,6 +311,8 @@ class SearchBench:
                 off, items = self.prep(st)
                 g.genie_search_spq_async(self.ix, off, items, self.k, self.max_items, sids, scts,
                                          sws, st)
+                if self.post:
+                    self.post(st, sids, scts)
 
             el_spq = self.timed(spq_step, steps, warmup)
             if not (torch.equal(sids, ref[0]) and torch.equal(scts, ref[1])):
@@ -815,9 +825,12 @@ def sequence_cpu_and_accuracy(inp, found_dist, budget_s: float):
 def bench_sequence(args, torch, genie, workloads):
     """Sequence search under edit distance (Section 5.1): 5,000,000
     title-like strings, 1,024 queries of 40 characters with 20 % of their
-    characters replaced.  A step decomposes the queries into ordered 3-grams,
-    takes the top-32 candidates by match count (c-PQ) and verifies them
-    (Algorithm 2, k = 1) with the certificate of Theorem 5.2."""
+    characters replaced.  A step decomposes the queries into ordered 3-grams
+    (device), takes the top-32 candidates by match count and verifies them
+    (Algorithm 2, k = 1) with the certificate of Theorem 5.2.  The candidate
+    search runs as plain c-PQ, with the learned gate (trained on other
+    queries over the same strings), and as GEN-SPQ; all three give the same
+    candidates, and every step includes decomposition and verification."""
     inp = workloads.sequence()
     log("sequence workload generated:", inp.n, "strings,", inp.chars.size, "bytes")
     sx = genie.SeqIndex(inp.chars, inp.offsets, inp.gram)
@@ -826,100 +839,58 @@ def bench_sequence(args, torch, genie, workloads):
     max_qlen = int(np.diff(inp.qoffsets).max())
     d_qc = torch.from_numpy(inp.qchars).cuda()
     d_qo = torch.from_numpy(inp.qoffsets.view(np.int64)).cuda()
+    items = torch.empty((d_qc.numel(), 3), dtype=torch.int32, device="cuda")
     ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
     dist = torch.empty_like(ids)
     cert = torch.empty(nq, dtype=torch.int32, device="cuda")
-    ws = sx.workspace(nq, d_qc.numel(), K)
 
-    def step():
-        genie.genie_seq_search_async(sx, d_qc, d_qo, max_qlen, K, k, ids, dist, cert, ws,
-                                     torch.cuda.current_stream())
+    def prep(st):
+        genie.genie_seq_decompose_async(sx, d_qc, d_qo, items, st)
+        return d_qo, items
 
-    def timed(fn):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        genie.genie_kernel_timing_read(reset=True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
+    def verify(st, c_ids, c_cts):
+        genie.genie_seq_verify_async(sx, d_qc, d_qo, max_qlen, c_ids, c_cts, k, ids, dist, cert,
+                                     st)
 
-    genie.genie_kernel_timing_enable(True)
-    el_eager = timed(step)
-    kt = genie.genie_kernel_timing_read(reset=True)
-    genie.genie_kernel_timing_enable(False)
-    log("sequence path, eager:", round(el_eager * 1e3 / args.steps, 3), "ms per step")
-    stats = genie.workspace_stats(ws)
-    if stats["status"] != 0:
-        raise RuntimeError(f"device status {stats}")
-    ref = (ids.clone(), dist.clone(), cert.clone())
-    el, launch = el_eager, "eager"
-    if use_graph(args, "sequence"):
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=side):
-            step()
-        torch.cuda.synchronize()
-        ids.zero_()
-        el = timed(graph.replay)
-        if not all(torch.equal(a, b) for a, b in zip((ids, dist, cert), ref)):
-            raise RuntimeError("graph replay and eager answers differ")
-        launch = "HIP graph replay"
+    ix = sx.match_index
+    sb = SearchBench(genie, torch, ix, nq, K, max_qlen, prep)
+    sb.post = verify
+    if not args.no_gate:
+        rng = np.random.default_rng(workloads.BASE_SEED + 100 + workloads.CONFIG_IDS["sequence"])
+        tq, to, _ = workloads.modified_queries(rng, inp.chars, inp.offsets,
+                                               args.gate_train_queries, 40, 0.2)
+        d_to = torch.from_numpy(to.view(np.int64)).cuda()
+        titems = genie.genie_seq_decompose_async(sx, torch.from_numpy(tq).cuda(), d_to)
+        sb.model = train_gate(genie, torch, ix, [(d_to, titems, 40, K)], args.gate_epochs)
     # items that name a keyword (the rest are empty and read nothing)
-    items = genie.genie_seq_decompose_async(sx, d_qc, d_qo)
+    prep(torch.cuda.current_stream())
     torch.cuda.synchronize()
     it = genie.as_uint32(items)
     s_total = int(np.count_nonzero(it[:, 1] <= it[:, 2]))
-    scan_ms = kt["scan_ms"] / max(1, kt["scan_launches"])
-    merge_ms = kt["merge_ms"] / max(1, kt["merge_launches"])
-    scanned = stats["postings_scanned"]
-    T = sx.info["n_tiles"]
-    alg_bytes = 2 * scanned + 12 * s_total + 8 * s_total * T + 8 * K * nq
-    achieved = alg_bytes / (scan_ms * 1e-3) / 1e9
+    res = sb.run(args.steps, args.warmup, s_total, graph=use_graph(args, "sequence"))
+    # the answers of the last timed step (every path verifies the same candidates)
+    torch.cuda.synchronize()
     dist_h, cert_h = genie.as_uint32(dist)[:, 0], genie.as_uint32(cert)
-    step_ms = el * 1e3 / args.steps
-    out = {"metric": "queries/sec, sequence search under edit distance, 5M strings, query "
-                     "length 40 with 20% modified, 3-grams, K=32 candidates, k=1; "
-                     "verification and certificate included",
-           "value": round(nq * args.steps / el, 1), "unit": "queries/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(step_ms, 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-           "data": "synthetic",
-           "config": {"workload": "sequence: 5,000,000 title-like strings (4..14 words of a "
-                                  "30,000-word Zipf(1.0) vocabulary, median 40 bytes); 1,024 "
-                                  "queries of 40 bytes, 20% of the bytes replaced; ordered "
-                                  "3-grams; K=32, k=1",
-                      "n_sequences": inp.n, "n_queries": nq, "K": K, "k": k, "gram": inp.gram,
-                      "launch": launch, "parallelism": "single GPU"},
-           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": measured_traffic("sequence"), "kernel": "scan_cpq_kernel",
-                        "kernel_ms": round(scan_ms, 4), "merge_kernel_ms": round(merge_ms, 4),
-                        "alg_bytes_per_launch": alg_bytes,
-                        "other_kernels_ms_per_step": round(
-                            el_eager * 1e3 / args.steps - scan_ms - merge_ms, 4)},
-           "plain_cpq": {"postings_per_step": scanned, "items_per_step": s_total,
-                         "eager_ms_per_step": round(el_eager * 1e3 / args.steps, 4),
-                         "ht_inserts_per_step": stats["ht_inserts"],
-                         "ht_overflow_tiles": stats["ht_overflow_tiles"]},
-           "quality": {"certified_fraction": round(float(cert_h.mean()), 4),
-                       "mean_top1_distance": round(float(dist_h.mean()), 3),
-                       "max_top1_distance": int(dist_h.max())},
-           "learned_gate": None, "gen_spq": None, "index": sx.info}
-    sx.free()
+    out = line(args, "sequence", res, {
+        "workload": "sequence: 5,000,000 title-like strings (4..14 words of a 30,000-word "
+                    "Zipf(1.0) vocabulary, median 40 bytes); 1,024 queries of 40 bytes, 20% of "
+                    "the bytes replaced; ordered 3-grams; K=32 candidates, k=1; decomposition "
+                    "and verification in every step",
+        "n_sequences": inp.n, "n_queries": nq, "K": K, "k": k, "gram": inp.gram})
+    out["quality"] = {"certified_fraction": round(float(cert_h.mean()), 4),
+                      "mean_top1_distance": round(float(dist_h.mean()), 3),
+                      "max_top1_distance": int(dist_h.max())}
+    out["index"] = sx.info
+    if out["learned_gate"]:
+        out["learned_gate"].update(train_queries=args.gate_train_queries,
+                                   epochs=args.gate_epochs)
     if not args.no_cpu_baseline and args.cpu_budget > 0:
         cpu, acc = sequence_cpu_and_accuracy(inp, dist_h, args.cpu_budget)
         out["cpu_baseline"] = cpu
         out["quality"].update(acc)
     else:
         out["cpu_baseline"] = None
+    sx.free()
     return out
 
 
