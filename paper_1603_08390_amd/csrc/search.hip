@@ -172,17 +172,57 @@ __device__ void ht_put(uint32_t *ht, uint32_t lg, uint32_t *misc, uint32_t lid, 
     }
 }
 
+// Number of the BITS-bit fields of `word` equal to v among those whose ids
+// (first, first + 1, ...) are below n.  Exact zero-field test: in x = word
+// xor (v in every field), a field is non-zero iff its high bit is set or its
+// low bits are; adding the low-bits mask to the low bits sets the high bit
+// exactly when they are non-zero (no carry leaves a field).
+template <int BITS>
+__device__ __forceinline__ uint32_t fields_equal(uint32_t word, uint32_t v, uint32_t n,
+                                                 uint32_t first) {
+    constexpr uint32_t CPW = 32 / BITS;
+    constexpr uint32_t ONES = BITS == 4 ? 0x11111111u : (BITS == 8 ? 0x01010101u : 0x00010001u);
+    constexpr uint32_t HI = ONES << (BITS - 1);
+    const uint32_t x = word ^ (v * ONES);
+    const uint32_t nonzero = (((x & ~HI) + ~HI) | x) & HI;
+    uint32_t zero = ~nonzero & HI;
+    if (first + CPW > n)   // fields at or past n are not objects of the tile
+        zero &= n > first ? HI >> ((CPW - (n - first)) * BITS) : 0u;
+    return __popc(zero);
+}
+
+constexpr uint32_t ilog2(uint32_t x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
+
+
+// Inclusive prefix sum over the 64 lanes of a wave by DPP moves, which stay
+// in the VALU (a shuffle is an LDS instruction and would queue behind the
+// counting atomics of the workgroup sharing the CU): shifts by 1, 2, 4 and 8
+// lanes inside each row of 16, then the last lane of a row added into the
+// next row (row_bcast:15) and lane 31 into the upper half (row_bcast:31).
+// Every lane in the wave must be active.
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
+    const uint32_t lane = threadIdx.x & 63, row_lane = lane & 15;
+    int v = (int)x, t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += row_lane >= 1 ? t : 0;
+    t = __builtin_amdgcn_mov_dpp(v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += row_lane >= 2 ? t : 0;
+    t = __builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += row_lane >= 4 ? t : 0;
+    t = __builtin_amdgcn_mov_dpp(v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += row_lane >= 8 ? t : 0;
+    t = __builtin_amdgcn_mov_dpp(v, 0x142, 0xF, 0xF, false);   // row_bcast:15
+    v += (lane & 31) >= 16 ? t : 0;
+    t = __builtin_amdgcn_mov_dpp(v, 0x143, 0xF, 0xF, false);   // row_bcast:31
+    v += lane >= 32 ? t : 0;
+    return (uint32_t)v;
+}
+
 // Exclusive prefix sum over the workgroup; returns the total in *total.
 template <int NT>
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32_t *total) {
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(incl, off, 64);
-        if (lane >= (uint32_t)off)
-            incl += y;
-    }
+    const uint32_t incl = wave_inclusive_sum(v);
     if (lane == 63)
         wave_sums[wave] = incl;
     __syncthreads();
@@ -528,25 +568,26 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         }
         spq_thr = lo;
     }
+    // settle: AT advances that raced with ZA increments are finished here.
+    // ZA is final after the barrier above, and the walk ends at the same AT
+    // from any start at or below it, so every thread settles for itself and
+    // the selection needs no barrier of its own.
+    uint32_t AT = lds_load(&misc[M_AT]);
+    while (AT <= s && lds_load(&za[AT]) >= k)
+        AT++;
+    // select from the counters after a Hash Table overflow (and in GEN-SPQ)
+    const bool from_counters = SPQ || lds_load(&misc[M_OVERFLOW]) != 0;
+    if constexpr (SPQ)
+        AT = spq_thr + 1;
     if (tid == 0) {
-        // settle: AT advances that raced with ZA increments are finished here
-        uint32_t a = misc[M_AT];
-        while (a <= s && za[a] >= k)
-            a++;
-        if constexpr (SPQ) {
-            a = spq_thr + 1;
-            misc[M_OVERFLOW] = 1;   // select from the counters
-        }
-        misc[M_AT] = a;
         const uint64_t scanned = misc[M_SCANNED];
         unsigned long long *stats = reinterpret_cast<unsigned long long *>(p.status + 2);
         atomicAdd(&stats[0], (unsigned long long)scanned);
-        if (misc[M_OVERFLOW] && !SPQ)
+        if (from_counters && !SPQ)
             atomicAdd(&stats[1], 1ull);
         atomicAdd(&stats[2], (unsigned long long)misc[M_INSERTS]);
         atomicAdd(&stats[3], (unsigned long long)misc[M_PASSES]);
     }
-    __syncthreads();
 
     if (DUMP) {
         for (uint32_t i = tid; i < tile_n; i += NT) {
@@ -557,7 +598,6 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     }
 
     // ---- select (Theorem 3.1): AT - 1 is the tile's k-th count
-    const uint32_t AT = misc[M_AT];
     const uint32_t thr = AT - 1;
     const uint32_t kk = min(k, tile_n);
     uint64_t *out = p.cand + row * k;
@@ -576,7 +616,7 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         if (pos < kk)
             out[pos] = make_key(old, (uint32_t)(gid0 + lid));
     };
-    if (!misc[M_OVERFLOW]) {
+    if (!from_counters) {
         for (uint32_t slot = tid; slot < cap; slot += NT) {
             const uint32_t cur = ht[slot];
             if (cur != 0 && (cur & 0xFFFFu) < tile_n)
@@ -586,37 +626,72 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         for (uint32_t lid = tid; lid < tile_n; lid += NT)
             claim(lid);
     }
-    __syncthreads();
-    const uint32_t n_above = min(misc[M_NABOVE], kk);
-    const uint32_t need = kk - n_above;
     // (2) count == AT - 1: the smallest ids, read from the counters in id
     //     order.  Thread t owns a contiguous range of counter words; a
     //     workgroup prefix count of the ties turns local order into the rank
-    //     in id order.
-    uint32_t emitted = n_above;
-    if (need > 0) {
-        constexpr uint32_t WPT = (NW + NT - 1) / NT;  // words per thread
-        const uint32_t wb = tid * WPT, we = min(NW, wb + WPT);
+    //     in id order.  The ties are counted in the same phase as the claims
+    //     above: a claim only turns a count >= AT into the emitted mark, a
+    //     field the tie count does not look at.
+    uint32_t emitted;
+    {
+        constexpr uint32_t WPT = NW / NT;  // words per thread
+        static_assert(WPT * NT == NW && WPT <= 64 && (WPT & (WPT - 1)) == 0, "tie pass layout");
+        const uint32_t wb = tid * WPT, we = wb + WPT;
+        // Counting is order-free, so each thread visits its words rotated by
+        // its lane group: lane a * (64 / WPT) + b reads word b * WPT +
+        // ((j + a) mod WPT) of the wave's block at step j, and the 64 lanes
+        // of one read hit 64 different LDS banks (in id order they would
+        // share 64 / WPT banks, stalling the counting of the workgroup that
+        // shares the CU).
+        const uint32_t rot = (tid & 63) >> (6 - ilog2(WPT));
         uint32_t mine = 0;
-        for (uint32_t w = wb; w < we; w++) {
-            const uint32_t word = bc[w];
-#pragma unroll
-            for (uint32_t f = 0; f < CPW; f++)
-                mine += (w * CPW + f < tile_n && ((word >> (f * BITS)) & MASK) == thr) ? 1u : 0u;
+#pragma unroll 8
+        for (uint32_t j = 0; j < WPT; j++) {
+            const uint32_t w = wb + ((j + rot) & (WPT - 1));
+            // claims may be updating other fields of this word: atomic read
+            mine += fields_equal<BITS>(lds_load(&bc[w]), thr, tile_n, w * CPW);
         }
-        uint32_t total = 0;
-        uint32_t r = block_exclusive_scan<NT>(mine, misc + M_WAVESUM, &total);
-        emitted += min(need, total);   // fewer only when AT started above the tile's k-th count
-        for (uint32_t w = wb; w < we && r < need && mine; w++) {
-            const uint32_t word = bc[w];
+        // rank of the thread's first tie in id order: a wave prefix sum, then
+        // the wave totals through LDS (one barrier, which also completes the
+        // claims; the totals are not written again before the next pair's
+        // barriers)
+        const uint32_t incl = wave_inclusive_sum(mine);
+        uint32_t *wsum = misc + M_WAVESUM;
+        if ((tid & 63) == 63)
+            wsum[tid >> 6] = incl;
+        __syncthreads();
+        const uint32_t n_above = min(misc[M_NABOVE], kk);
+        const uint32_t need = kk - n_above;
+        uint32_t before = 0, total = 0;
 #pragma unroll
-            for (uint32_t f = 0; f < CPW; f++) {
-                const uint32_t lid = w * CPW + f;
-                if (lid < tile_n && ((word >> (f * BITS)) & MASK) == thr) {
-                    if (r < need)
-                        out[n_above + r] = make_key(thr, (uint32_t)(gid0 + lid));
-                    r++;
-                }
+        for (uint32_t w = 0; w < NWAVE; w++) {
+            const uint32_t v = wsum[w];
+            before += w < (tid >> 6) ? v : 0u;
+            total += v;
+        }
+        uint32_t r = before + incl - mine;
+        // fewer than need only when AT started above the tile's k-th count
+        emitted = n_above + min(need, total);
+        if (mine && r < need) {
+            // the thread's words in id order, read a batch at a time so that
+            // the LDS latencies overlap
+            constexpr uint32_t B = WPT < 8 ? WPT : 8;
+            for (uint32_t w0 = wb; w0 < we && r < need; w0 += B) {
+                uint32_t wd[B];
+#pragma unroll
+                for (uint32_t u = 0; u < B; u++)
+                    wd[u] = bc[w0 + u];
+#pragma unroll
+                for (uint32_t u = 0; u < B; u++)
+#pragma unroll
+                    for (uint32_t f = 0; f < CPW; f++) {
+                        const uint32_t lid = (w0 + u) * CPW + f;
+                        if (lid < tile_n && ((wd[u] >> (f * BITS)) & MASK) == thr) {
+                            if (r < need)
+                                out[n_above + r] = make_key(thr, (uint32_t)(gid0 + lid));
+                            r++;
+                        }
+                    }
             }
         }
     }
