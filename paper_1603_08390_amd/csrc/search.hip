@@ -219,7 +219,9 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x) {
 }
 
 // Exclusive prefix sum over the workgroup; returns the total in *total.
-template <int NT>
+// TRAIL: end with a barrier, so that wave_sums may be written again at once
+// (callers that reach another barrier before the next write leave it out).
+template <int NT, bool TRAIL = true>
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32_t *total) {
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t incl = wave_inclusive_sum(v);
@@ -233,7 +235,8 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32
         before += (w < (int)wave) ? ws : 0;
         all += ws;
     }
-    __syncthreads();
+    if (TRAIL)
+        __syncthreads();
     *total = all;
     return before + incl - v;
 }
@@ -307,16 +310,18 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     }
     if (tid < 32)
         misc[tid] = (tid == M_AT) ? at0 : 0u;
-    __syncthreads();
     // Position Map lookup (Section 3.2), restricted to this tile: the keywords
     // of one dim are adjacent, so item (dim, lo, hi) is the single run
     // [toff[dim*V+lo], toff[dim*V+hi+1]) of the tile (padded to whole dwords).
+    // The lookup writes only the run table (the counters are cleared
+    // meanwhile); a thread's share of the scanned postings reaches misc
+    // after a barrier.
     const uint32_t *trow = p.toff + (uint64_t)t * p.nkeys1;
     const uint32_t *prow = p.tpad + (uint64_t)t * p.nkeys1;
-    for (uint32_t i = tid; i < s; i += NT) {
+    auto lookup = [&](uint32_t i, uint32_t &b, uint32_t &e, uint32_t &pads) {
         const uint32_t *it = p.items + 3 * (i0 + i);
         uint32_t dim = it[0], lo = it[1], hi = it[2];
-        uint32_t b = 0, e = 0, pads = 0;
+        b = e = pads = 0;
         if (dim >= p.d) {
             if (t == 0)
                 atomicOr(p.status, GENIE_STATUS_BAD_DIM);
@@ -334,25 +339,52 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                 pads = prow[key + hi + 1] - prow[key + lo];
             }
         }
-        sp_dw[i] = b >> 1;
-        sp_cum[i] = (e - b) >> 1;   // dwords of the run (temporary)
-        lds_add(&misc[M_SCANNED], (e - b) - pads);
-    }
-    __syncthreads();
-    // prefix counts of the runs' dwords (at most 1024 runs, 2 per thread)
-    {
+    };
+    if (s <= 64) {
+        // one item per lane of wave 0 and a wave prefix sum of the runs'
+        // dwords: the run table needs no barrier of its own
+        if (tid < 64) {
+            uint32_t b = 0, e = 0, pads = 0;
+            if (tid < s)
+                lookup(tid, b, e, pads);
+            const uint32_t dw = (e - b) >> 1;
+            const uint32_t incl = wave_inclusive_sum(dw);
+            if (tid < s) {
+                sp_dw[tid] = b >> 1;
+                sp_cum[tid] = incl - dw;
+            }
+            if (tid == 63)
+                sp_cum[s] = incl;
+            if (e - b - pads)   // misc was cleared by this wave above
+                lds_add(&misc[M_SCANNED], (e - b) - pads);
+        }
+        __syncthreads();
+    } else {
+        uint32_t my_scanned = 0;
+        for (uint32_t i = tid; i < s; i += NT) {
+            uint32_t b, e, pads;
+            lookup(i, b, e, pads);
+            sp_dw[i] = b >> 1;
+            sp_cum[i] = (e - b) >> 1;   // dwords of the run (temporary)
+            my_scanned += (e - b) - pads;
+        }
+        __syncthreads();
+        if (my_scanned)
+            lds_add(&misc[M_SCANNED], my_scanned);
+        // prefix counts of the runs' dwords (at most 1024 runs, 2 per thread)
         const uint32_t a0 = 2 * tid, a1 = 2 * tid + 1;
         const uint32_t c0 = a0 < s ? sp_cum[a0] : 0u, c1 = a1 < s ? sp_cum[a1] : 0u;
         uint32_t total = 0;
-        const uint32_t ex = block_exclusive_scan<NT>(c0 + c1, misc + M_WAVESUM, &total);
+        // the wave totals are next written after the barrier below
+        const uint32_t ex = block_exclusive_scan<NT, false>(c0 + c1, misc + M_WAVESUM, &total);
         if (a0 < s)
             sp_cum[a0] = ex;
         if (a1 < s)
             sp_cum[a1] = ex + c0;
         if (tid == 0)
             sp_cum[s] = total;
+        __syncthreads();
     }
-    __syncthreads();
 
     const uint64_t row = (uint64_t)q * p.tiles_total + p.tile_off + t;
     const uint64_t gid0 = p.id_base + tile0;   // global id of the tile's first object
