@@ -80,6 +80,60 @@ def test_argument_errors_without_device():
                                        None) == genie.GENIE_EINVAL
 
 
+def test_sequence_and_keyword_set_argument_errors_without_device():
+    lib = genie.load()
+    out = ctypes.c_void_p()
+    EINVAL, ERANGE = genie.GENIE_EINVAL, genie.GENIE_ERANGE
+    chars = np.frombuffer(b"abcabc", np.uint8).copy()
+    off = np.array([0, 3, 6], dtype=np.uint64)
+    c, o = chars.ctypes.data, off.ctypes.data
+    assert lib.genie_seq_build(c, None, 2, 3, 16, ctypes.byref(out)) == EINVAL
+    assert lib.genie_seq_build(c, o, 2, 3, 16, None) == EINVAL
+    assert lib.genie_seq_build(c, o, 0, 3, 16, ctypes.byref(out)) == EINVAL
+    for gram in (0, 9):
+        assert lib.genie_seq_build(c, o, 2, gram, 16, ctypes.byref(out)) == EINVAL
+        assert b"gram" in lib.genie_last_error()
+    assert lib.genie_seq_build(None, o, 2, 3, 16, ctypes.byref(out)) == EINVAL
+    first = np.array([1, 3, 6], dtype=np.uint64)
+    assert lib.genie_seq_build(c, first.ctypes.data, 2, 3, 16, ctypes.byref(out)) == EINVAL
+    assert b"offsets[0]" in lib.genie_last_error()
+    down = np.array([0, 4, 3], dtype=np.uint64)
+    assert lib.genie_seq_build(c, down.ctypes.data, 2, 3, 16, ctypes.byref(out)) == EINVAL
+    assert b"decrease" in lib.genie_last_error()
+    # tiles are checked by the keyword-set builder before any device call
+    assert lib.genie_seq_build(c, o, 2, 3, 14, ctypes.byref(out)) == EINVAL
+    assert b"tile_log2" in lib.genie_last_error()
+    # 256 byte values: 256^4 n-gram codes exceed the 2^24 table
+    every = np.arange(256, dtype=np.uint8)
+    eoff = np.array([0, 256], dtype=np.uint64)
+    assert lib.genie_seq_build(every.ctypes.data, eoff.ctypes.data, 1, 4, 16,
+                               ctypes.byref(out)) == ERANGE
+    assert b"n-gram codes" in lib.genie_last_error()
+    # calls on a null sequence index
+    assert lib.genie_seq_info_get(None, None) == EINVAL
+    assert lib.genie_seq_match_index(None) is None
+    assert lib.genie_seq_workspace_size(None, 1, 1, 1) == 0
+    assert lib.genie_seq_decompose_async(None, None, None, 0, 1, None, None) == EINVAL
+    assert lib.genie_seq_verify_async(None, None, None, 0, 1, 40, None, None, 32, 1, None, None,
+                                      None, None) == EINVAL
+    assert lib.genie_seq_search_async(None, None, None, 0, 1, 40, 32, 1, None, None, None, None,
+                                      0, None) == EINVAL
+    lib.genie_seq_free(None)
+    # keyword sets: null pointers, a key >= n_keys, decreasing offsets, tiles
+    keys = np.array([0, 1, 4], dtype=np.uint32)
+    ko = np.array([0, 2, 3], dtype=np.uint64)
+    k_, ko_ = keys.ctypes.data, ko.ctypes.data
+    assert lib.genie_build_index_sets(None, k_, 2, 5, 16, ctypes.byref(out)) == EINVAL
+    assert lib.genie_build_index_sets(ko_, k_, 2, 5, 16, None) == EINVAL
+    assert lib.genie_build_index_sets(ko_, k_, 2, 4, 16, ctypes.byref(out)) == EINVAL
+    assert b"out of range" in lib.genie_last_error()
+    kd = np.array([0, 3, 2], dtype=np.uint64)
+    assert lib.genie_build_index_sets(kd.ctypes.data, k_, 2, 5, 16, ctypes.byref(out)) == EINVAL
+    assert b"decrease" in lib.genie_last_error()
+    assert lib.genie_build_index_sets(ko_, k_, 2, 5, 17, ctypes.byref(out)) == EINVAL
+    assert lib.genie_build_index_sets(ko_, k_, 0, 5, 16, ctypes.byref(out)) == EINVAL
+
+
 def test_header_limits_match_binding():
     text = open(HEADER).read()
     for name, val in (("GENIE_MAX_K", genie.GENIE_MAX_K), ("GENIE_MAX_ITEMS", genie.GENIE_MAX_ITEMS),
@@ -92,9 +146,12 @@ def test_header_limits_match_binding():
 def test_oracle_shares_no_code_with_library():
     """The oracle's sources name nothing from the GPU library and the
     library's sources name nothing from the oracle."""
-    osrc = open(os.path.join(ROOT, "oracle", "genie_oracle.c")).read()
-    opy = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
-    assert "genie.h" not in osrc and "paper_1603_08390_amd" not in opy
+    odir = os.path.join(ROOT, "oracle")
+    for f in os.listdir(odir):
+        if f.endswith((".c", ".py", ".h")):
+            text = open(os.path.join(odir, f)).read()
+            assert "genie.h" not in text and "paper_1603_08390_amd" not in text, f
+            assert "csrc" not in text and "libgenie" not in text, f
     csrc = os.path.join(ROOT, "paper_1603_08390_amd", "csrc")
     for f in os.listdir(csrc):
         assert "oracle" not in open(os.path.join(csrc, f)).read().lower(), f
