@@ -88,6 +88,33 @@ __device__ __forceinline__ bool lds_cas(uint32_t *p, uint32_t expect, uint32_t d
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The last run starting at or before p0, given lo with sp_cum[lo] <= p0 and
+// p0 < sp_cum[s] (the run starts ascend): a galloping search from lo, then
+// bisection.  The run found is never empty, since the run after it starts
+// past p0.  Kept out of line: it serves the long jumps of the run cursor
+// over short runs.
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;   // an LDS word
+__device__ __attribute__((noinline)) uint32_t last_run_at_or_before(lds_u32 *sp_cum, uint32_t lo,
+                                                                    uint32_t s, uint32_t p0) {
+    uint32_t hi = s, step = 1;   // sp_cum[lo] <= p0 < sp_cum[hi]
+    while (lo + step < s) {
+        if (sp_cum[lo + step] > p0) {
+            hi = lo + step;
+            break;
+        }
+        lo += step;
+        step <<= 1;
+    }
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sp_cum[mid] <= p0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // misc words at the start of the LDS block
 enum : int {
     M_AT = 0, M_NABOVE = 1, M_OVERFLOW = 2, M_INSERTS = 3, M_SCANNED = 4, M_PASSES = 5,
@@ -425,6 +452,10 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     uint32_t si = 0, c_lo = 0;
     uint32_t c_hi = s ? __builtin_amdgcn_readfirstlane(sp_cum[1]) : 0u;
     uint32_t dwb = s ? __builtin_amdgcn_readfirstlane(sp_dw[0]) : 0u;
+    // A wave's next piece lies NWAVE pieces ahead; when the runs average
+    // fewer than 256 dwords that is past 16 runs or more on average, and the
+    // cursor finds its run by a galloping search instead of run by run.
+    const bool short_runs = total_dw < 256u * s;
     // dword offsets (in the tile) of the U pieces that start at stream
     // position cb; the cursor only moves forward, and pieces past the end
     // read the tile's trailing padding dwords
@@ -436,10 +467,24 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                 if (p0 >= total_dw) {
                     off[u] = sent_dw + lane;
                 } else {
-                    while (p0 >= c_hi) {   // next run (runs of no dwords are skipped)
+                    if (p0 >= c_hi) {   // the run holding p0
                         si++;
                         c_lo = c_hi;
                         c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
+                        if (p0 >= c_hi) {
+                            if (short_runs) {
+                                si = __builtin_amdgcn_readfirstlane(
+                                    last_run_at_or_before((lds_u32 *)sp_cum, si + 1, s, p0));
+                                c_lo = __builtin_amdgcn_readfirstlane(sp_cum[si]);
+                                c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
+                            } else {
+                                while (p0 >= c_hi) {   // runs of no dwords are skipped
+                                    si++;
+                                    c_lo = c_hi;
+                                    c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
+                                }
+                            }
+                        }
                         dwb = __builtin_amdgcn_readfirstlane(sp_dw[si]);
                     }
                     if (p0 + 64 <= c_hi) {
