@@ -129,7 +129,17 @@ static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nk
     std::vector<uint64_t> tile_size(T);
     std::vector<uint64_t> &tile_base = h->tile_base;
     tile_base.assign(T + 1, 0);
-    std::atomic<int> bad{0}, overflow{0};
+    std::atomic<int> bad{0}, overflow{0}, nomem{0};
+    // a thread that cannot allocate reports it instead of ending the process
+    auto guarded = [&](const auto &body) {
+        return [&nomem, &body]() {
+            try {
+                body();
+            } catch (const std::bad_alloc &) {
+                nomem.store(1);
+            }
+        };
+    };
     std::atomic<uint32_t> next{0};
     auto count_tiles = [&]() {
         for (;;) {
@@ -165,9 +175,13 @@ static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nk
     {
         std::vector<std::thread> pool;
         for (unsigned i = 0; i < nth; i++)
-            pool.emplace_back(count_tiles);
+            pool.emplace_back(guarded(count_tiles));
         for (auto &th : pool)
             th.join();
+    }
+    if (nomem.load()) {
+        set_error("host allocation failed while building the index");
+        return GENIE_ENOMEM;
     }
     if (bad.load()) {
         set_error("a keyword is out of range (n_buckets %u, keywords %llu)", V,
@@ -213,9 +227,13 @@ static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nk
     {
         std::vector<std::thread> pool;
         for (unsigned i = 0; i < nth; i++)
-            pool.emplace_back(fill_tiles);
+            pool.emplace_back(guarded(fill_tiles));
         for (auto &th : pool)
             th.join();
+    }
+    if (nomem.load()) {
+        set_error("host allocation failed while building the index");
+        return GENIE_ENOMEM;
     }
     h->n = n;
     h->d = d;

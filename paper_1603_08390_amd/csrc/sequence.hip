@@ -402,15 +402,20 @@ extern "C" int genie_seq_build(const uint8_t *chars, const uint64_t *offsets, ui
             std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
         auto for_sequences = [&](const auto &body) {
             std::atomic<uint64_t> next{0};
+            std::atomic<int> nomem{0};
             const uint64_t chunk = 4096;
             auto worker = [&]() {
-                std::vector<uint64_t> scratch;
-                for (;;) {
-                    const uint64_t s0 = next.fetch_add(chunk);
-                    if (s0 >= n)
-                        break;
-                    for (uint64_t s = s0; s < std::min(n, s0 + chunk); s++)
-                        body(s, scratch);
+                try {   // a thread that cannot allocate reports it
+                    std::vector<uint64_t> scratch;
+                    for (;;) {
+                        const uint64_t s0 = next.fetch_add(chunk);
+                        if (s0 >= n || nomem.load())
+                            break;
+                        for (uint64_t s = s0; s < std::min(n, s0 + chunk); s++)
+                            body(s, scratch);
+                    }
+                } catch (const std::bad_alloc &) {
+                    nomem.store(1);
                 }
             };
             std::vector<std::thread> pool;
@@ -418,6 +423,8 @@ extern "C" int genie_seq_build(const uint8_t *chars, const uint64_t *offsets, ui
                 pool.emplace_back(worker);
             for (auto &th : pool)
                 th.join();
+            if (nomem.load())
+                throw std::bad_alloc();   // caught below: GENIE_ENOMEM
         };
         // codes, then occurrence ranks by sorting (code, window) within a
         // sequence, then the largest occurrence count of every code
