@@ -147,38 +147,52 @@ __device__ __forceinline__ float wload(const uint16_t *w, int i) {
 }
 __device__ __forceinline__ float wload(const float *w, int i) { return w[i]; }
 
-// Forward for kQB samples; thread j owns hidden unit j.  Leaves the hidden
+// Forward for QB samples; thread j owns hidden unit j.  Leaves the hidden
 // activations in h1s / h2s and the outputs in outs.
-template <typename WT>
+template <typename WT, int QB>
 __device__ void mlp_forward_block(const WT *w, const float (*xs)[kF + 1], float (*h1s)[kH + 1],
                                   float (*h2s)[kH + 1], float *outs) {
     const int j = threadIdx.x;
+    // Every output is the same fixed-order chain: bias, then one fma per
+    // input in ascending order (batch-invariant); the loops run over the
+    // inputs outside the samples, so each weight is read once per workgroup.
     {
-        float wr[kF];
-#pragma unroll
-        for (int i = 0; i < kF; i++)
-            wr[i] = wload(w, kOffW1 + j * kF + i);
+        float acc[QB];
         const float b = wload(w, kOffB1 + j);
-        for (int q = 0; q < kQB; q++) {
-            float acc = b;
 #pragma unroll
-            for (int i = 0; i < kF; i++)
-                acc = fmaf(wr[i], xs[q][i], acc);
-            h1s[q][j] = fmaxf(acc, 0.0f);
+        for (int q = 0; q < QB; q++)
+            acc[q] = b;
+#pragma unroll 8
+        for (int i = 0; i < kF; i++) {
+            const float wi = wload(w, kOffW1 + j * kF + i);
+#pragma unroll
+            for (int q = 0; q < QB; q++)
+                acc[q] = fmaf(wi, xs[q][i], acc[q]);
         }
+#pragma unroll
+        for (int q = 0; q < QB; q++)
+            h1s[q][j] = fmaxf(acc[q], 0.0f);
     }
     __syncthreads();
     {
+        float acc[QB];
         const float b = wload(w, kOffB2 + j);
-        for (int q = 0; q < kQB; q++) {
-            float acc = b;
-            for (int i = 0; i < kH; i++)
-                acc = fmaf(wload(w, kOffW2 + j * kH + i), h1s[q][i], acc);
-            h2s[q][j] = fmaxf(acc, 0.0f);
+#pragma unroll
+        for (int q = 0; q < QB; q++)
+            acc[q] = b;
+#pragma unroll 8
+        for (int i = 0; i < kH; i++) {
+            const float wi = wload(w, kOffW2 + j * kH + i);
+#pragma unroll
+            for (int q = 0; q < QB; q++)
+                acc[q] = fmaf(wi, h1s[q][i], acc[q]);
         }
+#pragma unroll
+        for (int q = 0; q < QB; q++)
+            h2s[q][j] = fmaxf(acc[q], 0.0f);
     }
     __syncthreads();
-    if (j < kQB) {
+    if (j < QB) {
         float acc = wload(w, kOffB3);
         for (int i = 0; i < kH; i++)
             acc = fmaf(wload(w, kOffW3 + i), h2s[j][i], acc);
@@ -187,21 +201,24 @@ __device__ void mlp_forward_block(const WT *w, const float (*xs)[kF + 1], float 
     __syncthreads();
 }
 
+// Prediction: kQF samples per workgroup, so that a batch of about a thousand
+// queries spreads over the device.
+constexpr int kQF = 4;
 template <typename WT>
 __global__ __launch_bounds__(kH) void gate_forward_kernel(const WT *w, const float *x, uint32_t n,
                                                           float *out) {
-    __shared__ float xs[kQB][kF + 1];
-    __shared__ float h1s[kQB][kH + 1];
-    __shared__ float h2s[kQB][kH + 1];
-    __shared__ float outs[kQB];
-    const uint64_t q0 = (uint64_t)blockIdx.x * kQB;
-    for (int e = threadIdx.x; e < kQB * kF; e += kH) {
+    __shared__ float xs[kQF][kF + 1];
+    __shared__ float h1s[kQF][kH + 1];
+    __shared__ float h2s[kQF][kH + 1];
+    __shared__ float outs[kQF];
+    const uint64_t q0 = (uint64_t)blockIdx.x * kQF;
+    for (int e = threadIdx.x; e < kQF * kF; e += kH) {
         const int q = e / kF, i = e % kF;
         xs[q][i] = q0 + q < n ? x[(q0 + q) * kF + i] : 0.0f;
     }
     __syncthreads();
-    mlp_forward_block(w, xs, h1s, h2s, outs);
-    if (threadIdx.x < kQB && q0 + threadIdx.x < n)
+    mlp_forward_block<WT, kQF>(w, xs, h1s, h2s, outs);
+    if (threadIdx.x < kQF && q0 + threadIdx.x < n)
         out[q0 + threadIdx.x] = outs[threadIdx.x];
 }
 
@@ -225,7 +242,7 @@ __global__ __launch_bounds__(kH) void gate_backward_kernel(const WT *w, const fl
         xs[q][i] = (uint32_t)q < nb ? x[(q0 + q) * kF + i] : 0.0f;
     }
     __syncthreads();
-    mlp_forward_block(w, xs, h1s, h2s, outs);
+    mlp_forward_block<WT, kQB>(w, xs, h1s, h2s, outs);
     if (j < kQB) {
         float g = 0.0f;
         if ((uint32_t)j < nb) {
@@ -400,7 +417,7 @@ extern "C" int genie_gate_forward_async(const uint16_t *d_w_bf16, const float *d
         set_error("null pointer");
         return GENIE_EINVAL;
     }
-    dim3 grid((n + kQB - 1) / kQB);
+    dim3 grid((n + kQF - 1) / kQF);
     if (d_w_bf16)
         hipLaunchKernelGGL(gate_forward_kernel<uint16_t>, grid, dim3(kH), 0, (hipStream_t)stream,
                            d_w_bf16, d_x, n, d_out);

@@ -51,7 +51,14 @@ struct ScanParams {
     uint32_t tile_off, tiles_total;
     uint32_t spq;           // 1: GEN-SPQ ablation (count everything, then select)
     uint32_t key_sets;      // 1: keyword-set index, every item names one keyword
+    uint32_t rows_loop;     // 1: the pairs of the qcount rows only, by resident workgroups
 };
+
+// Schedules of the scan kernel: one workgroup per pair; persistent
+// workgroups over per-XCD pair counters; resident workgroups looping over
+// the pairs of the rows counted on the device (the gated search's fallback
+// pass, which usually has none).
+enum : int { kSchedGrid = 0, kSchedQueue = 1, kSchedRows = 2 };
 
 struct MergeParams {
     const uint64_t *cand;
@@ -778,7 +785,7 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         p.tile_kth[row] = thr;
 }
 
-template <int BITS, int NT, int U, bool DUMP, int LG, bool PERSIST, bool SPQ = false>
+template <int BITS, int NT, int U, bool DUMP, int LG, int SCHED, bool SPQ = false>
 __global__ __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(scan_waves_per_eu<BITS, NT, LG>())))
 void scan_cpq_kernel(ScanParams p) {
@@ -793,10 +800,21 @@ void scan_cpq_kernel(ScanParams p) {
     // and its L2 keeps serving the same tile's postings.
     const uint32_t bid = blockIdx.x;
     const uint64_t npairs = (uint64_t)p.nq * p.n_tiles;
-    if constexpr (!PERSIST) {   // one workgroup per pair
+    if constexpr (SCHED == kSchedGrid) {   // one workgroup per pair
         const uint64_t pair = (uint64_t)(bid & 7) * p.per_xcd + (bid >> 3);
         if (pair < npairs)
             scan_pair<BITS, NT, U, DUMP, LG, SPQ>(p, pair, bc, smem);
+    } else if constexpr (SCHED == kSchedRows) {
+        // only the pairs of the qcount rows: pair index i is tile i / qc of
+        // row i mod qc; no work, and no dispatch of one workgroup per pair,
+        // when the count is 0
+        const uint32_t qc = *p.qcount;
+        const uint64_t n = (uint64_t)qc * p.n_tiles;
+        for (uint64_t i = bid; i < n; i += gridDim.x) {
+            const uint64_t t = i / qc, qrow = i - t * qc;
+            scan_pair<BITS, NT, U, DUMP, LG, SPQ>(p, t * p.nq + qrow, bc, smem);
+            __syncthreads();   // the next pair reuses the LDS
+        }
     } else {
         // Persistent schedule: as many workgroups as fit the device at once,
         // each taking the next pair of its XCD's slice from that slice's
@@ -910,10 +928,9 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
 }
 
 // Status block: flags, statistics, the fallback count and the persistent
-// schedule's pair counters (words 16..23 for the scan, 24..31 for the
-// fallback pass).
+// schedule's pair counters (words 16..23; words 24..31 are spare).
 constexpr uint32_t kStatusWords = 32;
-constexpr uint32_t kWorkWord = 16, kFallbackWorkWord = 24;
+constexpr uint32_t kWorkWord = 16;
 __global__ void clear_status_kernel(uint32_t *status) {
     if (threadIdx.x < kStatusWords)
         status[threadIdx.x] = 0;
@@ -924,14 +941,16 @@ int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipS
     // the count dump (match-count entry point) always runs 1024 x 4, one
     // workgroup per pair
     // (the GEN-SPQ ablation likewise)
-    const void *kern = dump ? (const void *)scan_cpq_kernel<BITS, 1024, 4, true, LG, false>
-                     : sp.spq ? (const void *)scan_cpq_kernel<BITS, 1024, 4, false, LG, false, true>
-                     : sp.work ? (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, true>
-                               : (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, false>;
+    const void *kern =
+        dump ? (const void *)scan_cpq_kernel<BITS, 1024, 4, true, LG, kSchedGrid>
+        : sp.spq ? (const void *)scan_cpq_kernel<BITS, 1024, 4, false, LG, kSchedGrid, true>
+        : sp.rows_loop ? (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, kSchedRows>
+        : sp.work ? (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, kSchedQueue>
+                  : (const void *)scan_cpq_kernel<BITS, NT, U, false, LG, kSchedGrid>;
     const int nt = (dump || sp.spq) ? 1024 : NT;
     GENIE_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    if (sp.work && !dump) {
-        // persistent schedule: the workgroups that fit the device at once
+    if ((sp.work || sp.rows_loop) && !dump && !sp.spq) {
+        // persistent and row schedules: the workgroups that fit the device at once
         // (a multiple of 8, so that every XCD has the same number)
         int dev = 0, cus = 0, per_cu = 0;
         GENIE_HIP(hipGetDevice(&dev));
@@ -1142,7 +1161,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     fp.gate = nullptr;
     fp.qlist = fb_list;
     fp.qcount = fb_count;
-    fp.work = ix->scan_persistent ? sp.status + kFallbackWorkWord : nullptr;
+    fp.work = nullptr;
+    fp.rows_loop = 1;   // resident workgroups over the flagged rows' pairs only
     rc = dispatch_scan(shape.bits, ix->scan_threads, ix->scan_unroll, ix->tile_log2, fp, false,
                        shape.lds_bytes, grid, stream);
     if (rc)
