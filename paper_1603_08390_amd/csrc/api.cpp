@@ -302,6 +302,14 @@ int build_host_index_sets(const uint64_t *obj_offsets, const uint32_t *keys, uin
 
 namespace genie {
 
+void interleave_offsets(const HostIndex &h, uint32_t *dst) {
+    const uint64_t m = h.toff.size();
+    for (uint64_t i = 0; i < m; i++) {
+        dst[2 * i] = h.toff[i];
+        dst[2 * i + 1] = h.tpad[i];
+    }
+}
+
 int upload_host_index(const HostIndex &h, genie_index **out) {
     const uint32_t T = h.n_tiles;
     genie_index *ix = new (std::nothrow) genie_index;
@@ -321,23 +329,32 @@ int upload_host_index(const HostIndex &h, genie_index **out) {
     ix->key_sets = h.key_sets;
     hipError_t e = hipGetDevice(&ix->device);
     size_t bp = h.post.size() * sizeof(uint16_t), bb = h.tile_base.size() * sizeof(uint64_t),
-           bt = h.toff.size() * sizeof(uint32_t), bk = h.kcum.size() * sizeof(uint64_t);
+           bt = 2 * h.toff.size() * sizeof(uint32_t), bk = h.kcum.size() * sizeof(uint64_t);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->post, bp);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->tile_base, bb);
-    if (e == hipSuccess) e = hipMalloc((void **)&ix->toff, bt);
-    if (e == hipSuccess) e = hipMalloc((void **)&ix->tpad, bt);
+    if (e == hipSuccess) e = hipMalloc((void **)&ix->tix, bt);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->kcum, bk);
     if (e == hipSuccess) e = hipMemcpy(ix->kcum, h.kcum.data(), bk, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->post, h.post.data(), bp, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->tile_base, h.tile_base.data(), bb, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ix->toff, h.toff.data(), bt, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ix->tpad, h.tpad.data(), bt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        std::vector<uint32_t> tix;
+        try {
+            tix.resize(2 * h.toff.size());
+        } catch (const std::bad_alloc &) {
+            set_error("out of host memory for the index offsets");
+            genie_free_index(ix);
+            return GENIE_ENOMEM;
+        }
+        interleave_offsets(h, tix.data());
+        e = hipMemcpy(ix->tix, tix.data(), bt, hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         int rc = hip_fail(e, "index upload");
         genie_free_index(ix);
         return rc;
     }
-    ix->device_bytes = bp + bb + 2 * bt + bk;
+    ix->device_bytes = bp + bb + bt + bk;
     *out = ix;
     return GENIE_OK;
 }
@@ -390,8 +407,7 @@ extern "C" void genie_free_index(genie_index *ix) {
         (void)hipSetDevice(ix->device);
     if (ix->post) (void)hipFree(ix->post);
     if (ix->tile_base) (void)hipFree(ix->tile_base);
-    if (ix->toff) (void)hipFree(ix->toff);
-    if (ix->tpad) (void)hipFree(ix->tpad);
+    if (ix->tix) (void)hipFree(ix->tix);
     if (ix->kcum) (void)hipFree(ix->kcum);
     if (sw)
         (void)hipSetDevice(cur);

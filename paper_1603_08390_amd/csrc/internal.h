@@ -44,8 +44,9 @@ struct genie_index {
     // device arrays
     uint16_t *post = nullptr;      // tile-major, keyword-major, ascending local ids (+ pad)
     uint64_t *tile_base = nullptr; // n_tiles + 1 element offsets of each tile in post
-    uint32_t *toff = nullptr;      // n_tiles rows of nkeys + 1 padded offsets, relative to tile_base
-    uint32_t *tpad = nullptr;      // n_tiles rows of nkeys + 1 counts of padded runs before a keyword
+    // n_tiles rows of nkeys + 1 pairs {padded offset relative to tile_base,
+    // padded runs before the keyword}: one lookup reads both from one line
+    uint32_t *tix = nullptr;
     uint64_t *kcum = nullptr;      // nkeys + 1 prefix counts of postings per keyword (all tiles)
     uint64_t stored_postings = 0;  // elements in post (real + padding + trailing sentinels)
     uint64_t device_bytes = 0;
@@ -75,6 +76,9 @@ int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
 int build_host_index_sets(const uint64_t *obj_offsets, const uint32_t *keys, uint64_t n,
                           uint32_t n_keys, uint32_t tile_log2, HostIndex *h);
 int upload_host_index(const HostIndex &h, genie_index **out);
+// Writes the device form of h's offset rows: 2 * h.toff.size() words,
+// {toff[i], tpad[i]} at 2i and 2i + 1.
+void interleave_offsets(const HostIndex &h, uint32_t *dst);
 
 void set_error(const char *fmt, ...);
 void clear_error();
@@ -123,7 +127,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
 struct IndexView {
     const uint16_t *post = nullptr;
     const uint64_t *tile_base = nullptr;
-    const uint32_t *toff = nullptr, *tpad = nullptr;
+    const uint32_t *tix = nullptr;   // offset pairs, as in genie_index
     uint64_t n = 0, nkeys = 0;
     uint32_t d = 0, V = 0, n_tiles = 0, tile_log2 = 0;
     int scan_threads = kScanThreadsDefault, scan_unroll = kScanUnrollDefault;

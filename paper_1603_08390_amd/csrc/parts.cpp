@@ -27,14 +27,14 @@ struct PartHost {
     uint64_t nkeys = 0;
     uint16_t *post = nullptr;       // pinned host arrays of the part's index
     uint64_t *tile_base = nullptr;
-    uint32_t *toff = nullptr, *tpad = nullptr;
+    uint32_t *tix = nullptr;        // offset pairs, as in genie_index
     size_t post_bytes = 0, base_bytes = 0, off_bytes = 0;
 };
 
 struct Slot {
     uint16_t *post = nullptr;
     uint64_t *tile_base = nullptr;
-    uint32_t *toff = nullptr, *tpad = nullptr;
+    uint32_t *tix = nullptr;
     hipEvent_t copied = nullptr, scanned = nullptr;
 };
 
@@ -57,14 +57,12 @@ void free_parts(genie_parts *ps) {
     for (PartHost &p : ps->parts) {
         if (p.post) (void)hipHostFree(p.post);
         if (p.tile_base) (void)hipHostFree(p.tile_base);
-        if (p.toff) (void)hipHostFree(p.toff);
-        if (p.tpad) (void)hipHostFree(p.tpad);
+        if (p.tix) (void)hipHostFree(p.tix);
     }
     for (Slot &s : ps->slot) {
         if (s.post) (void)hipFree(s.post);
         if (s.tile_base) (void)hipFree(s.tile_base);
-        if (s.toff) (void)hipFree(s.toff);
-        if (s.tpad) (void)hipFree(s.tpad);
+        if (s.tix) (void)hipFree(s.tix);
         if (s.copied) (void)hipEventDestroy(s.copied);
         if (s.scanned) (void)hipEventDestroy(s.scanned);
     }
@@ -116,21 +114,19 @@ extern "C" int genie_parts_build(const uint32_t *values, uint64_t n, uint32_t d,
         p.nkeys = h.nkeys;
         p.post_bytes = h.post.size() * sizeof(uint16_t);
         p.base_bytes = h.tile_base.size() * sizeof(uint64_t);
-        p.off_bytes = h.toff.size() * sizeof(uint32_t);
+        p.off_bytes = 2 * h.toff.size() * sizeof(uint32_t);
         // pinned host copies: the copies to the device run asynchronously
         e = hipHostMalloc((void **)&p.post, p.post_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&p.tile_base, p.base_bytes, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&p.toff, p.off_bytes, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&p.tpad, p.off_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&p.tix, p.off_bytes, hipHostMallocDefault);
         ps->parts.push_back(p);
         if (e != hipSuccess)
             break;
         PartHost &q = ps->parts.back();
         std::memcpy(q.post, h.post.data(), q.post_bytes);
         std::memcpy(q.tile_base, h.tile_base.data(), q.base_bytes);
-        std::memcpy(q.toff, h.toff.data(), q.off_bytes);
-        std::memcpy(q.tpad, h.tpad.data(), q.off_bytes);
-        ps->host_bytes += q.post_bytes + q.base_bytes + 2 * q.off_bytes;
+        interleave_offsets(h, q.tix);
+        ps->host_bytes += q.post_bytes + q.base_bytes + q.off_bytes;
         max_post = std::max(max_post, q.post_bytes);
         max_base = std::max(max_base, q.base_bytes);
         max_off = std::max(max_off, q.off_bytes);
@@ -140,8 +136,7 @@ extern "C" int genie_parts_build(const uint32_t *values, uint64_t n, uint32_t d,
     for (Slot &s : ps->slot) {
         if (e == hipSuccess) e = hipMalloc((void **)&s.post, max_post);
         if (e == hipSuccess) e = hipMalloc((void **)&s.tile_base, max_base);
-        if (e == hipSuccess) e = hipMalloc((void **)&s.toff, max_off);
-        if (e == hipSuccess) e = hipMalloc((void **)&s.tpad, max_off);
+        if (e == hipSuccess) e = hipMalloc((void **)&s.tix, max_off);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.scanned, hipEventDisableTiming);
     }
@@ -151,7 +146,7 @@ extern "C" int genie_parts_build(const uint32_t *values, uint64_t n, uint32_t d,
         free_parts(ps);
         return rc;
     }
-    ps->device_bytes = 2 * (max_post + max_base + 2 * max_off);
+    ps->device_bytes = 2 * (max_post + max_base + max_off);
     *out = ps;
     return GENIE_OK;
 }
@@ -228,17 +223,14 @@ extern "C" int genie_parts_search_async(genie_parts *ps, const uint64_t *d_q_off
                                  ps->copy_stream));
         GENIE_HIP(hipMemcpyAsync(s.tile_base, p.tile_base, p.base_bytes, hipMemcpyHostToDevice,
                                  ps->copy_stream));
-        GENIE_HIP(hipMemcpyAsync(s.toff, p.toff, p.off_bytes, hipMemcpyHostToDevice,
-                                 ps->copy_stream));
-        GENIE_HIP(hipMemcpyAsync(s.tpad, p.tpad, p.off_bytes, hipMemcpyHostToDevice,
+        GENIE_HIP(hipMemcpyAsync(s.tix, p.tix, p.off_bytes, hipMemcpyHostToDevice,
                                  ps->copy_stream));
         GENIE_HIP(hipEventRecord(s.copied, ps->copy_stream));
         GENIE_HIP(hipStreamWaitEvent(st, s.copied, 0));
         IndexView v;
         v.post = s.post;
         v.tile_base = s.tile_base;
-        v.toff = s.toff;
-        v.tpad = s.tpad;
+        v.tix = s.tix;
         v.n = p.n;
         v.nkeys = p.nkeys;
         v.d = ps->d;

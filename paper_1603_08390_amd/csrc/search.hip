@@ -24,10 +24,9 @@ namespace {
 struct ScanParams {
     const uint16_t *post;
     const uint64_t *tile_base;
-    const uint32_t *toff;
-    const uint32_t *tpad;
+    const uint2 *tix;       // per tile, nkeys1 pairs {padded offset, padded runs before}
     uint64_t n;
-    uint64_t nkeys1;        // keywords + 1 (row length of toff)
+    uint64_t nkeys1;        // keywords + 1 (row length of tix)
     uint32_t d, V, n_tiles;
     const uint64_t *q_off;
     const uint32_t *items;  // 3 words per item
@@ -346,12 +345,13 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         misc[tid] = (tid == M_AT) ? at0 : 0u;
     // Position Map lookup (Section 3.2), restricted to this tile: the keywords
     // of one dim are adjacent, so item (dim, lo, hi) is the single run
-    // [toff[dim*V+lo], toff[dim*V+hi+1]) of the tile (padded to whole dwords).
+    // [off[dim*V+lo], off[dim*V+hi+1]) of the tile (padded to whole dwords);
+    // each keyword's offset and its count of padded runs before it sit in one
+    // pair, so an item's two endpoints cost one or two 8-byte reads.
     // The lookup writes only the run table (the counters are cleared
     // meanwhile); a thread's share of the scanned postings reaches misc
     // after a barrier.
-    const uint32_t *trow = p.toff + (uint64_t)t * p.nkeys1;
-    const uint32_t *prow = p.tpad + (uint64_t)t * p.nkeys1;
+    const uint2 *xrow = p.tix + (uint64_t)t * p.nkeys1;
     auto lookup = [&](uint32_t i, uint32_t &b, uint32_t &e, uint32_t &pads) {
         const uint32_t *it = p.items + 3 * (i0 + i);
         uint32_t dim = it[0], lo = it[1], hi = it[2];
@@ -368,9 +368,10 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                     atomicOr(p.status, GENIE_STATUS_RANGE_ON_SET);
             } else if (lo <= hi) {
                 const uint64_t key = (uint64_t)dim * p.V;
-                b = trow[key + lo];
-                e = trow[key + hi + 1];
-                pads = prow[key + hi + 1] - prow[key + lo];
+                const uint2 x0 = xrow[key + lo], x1 = xrow[key + hi + 1];
+                b = x0.x;
+                e = x1.x;
+                pads = x1.y - x0.y;
             }
         }
     };
@@ -449,7 +450,7 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     // without a bounds test; lanes past the end read the tile's trailing
     // all-sentinel dwords.
     const char *tile_bytes = reinterpret_cast<const char *>(p.post) + 2 * p.tile_base[t];
-    const uint32_t sent_dw = trow[p.nkeys1 - 1] >> 1;   // trailing sentinel dwords of the tile
+    const uint32_t sent_dw = xrow[p.nkeys1 - 1].x >> 1;   // trailing sentinel dwords of the tile
     const uint32_t k = p.k;
     // wave-uniform values, so that the run cursor lives in scalar registers
     const uint32_t total_dw = __builtin_amdgcn_readfirstlane(sp_cum[s]);
@@ -1021,8 +1022,7 @@ int launch_part_scan(const IndexView &v, uint64_t id_base, uint32_t tile_off,
     ScanParams sp{};
     sp.post = v.post;
     sp.tile_base = v.tile_base;
-    sp.toff = v.toff;
-    sp.tpad = v.tpad;
+    sp.tix = reinterpret_cast<const uint2 *>(v.tix);
     sp.n = v.n;
     sp.nkeys1 = v.nkeys + 1;
     sp.d = v.d;
@@ -1094,8 +1094,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     ScanParams sp{};
     sp.post = ix->post;
     sp.tile_base = ix->tile_base;
-    sp.toff = ix->toff;
-    sp.tpad = ix->tpad;
+    sp.tix = reinterpret_cast<const uint2 *>(ix->tix);
     sp.n = ix->n;
     sp.nkeys1 = ix->nkeys + 1;
     sp.d = ix->d;
