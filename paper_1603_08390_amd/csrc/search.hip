@@ -843,14 +843,19 @@ void scan_cpq_kernel(ScanParams p) {
     }
 }
 
-// Per query: keep candidates whose count reaches the largest tile k-th count
-// (the global k-th count is at least that), sort them by key, emit top k.
+// Per query: the largest tile k-th count is a floor of the global k-th
+// count; a histogram of the candidates' counts above the floor gives the
+// global k-th count itself (or a floor of it when it lies past the top bin).
+// Only candidates reaching it are sorted by key; emit the top k.
 constexpr int kMergeBuf = 4096;   // keys held in LDS
 constexpr int kMergeChunk = 2048; // candidates read per round
+constexpr int kMergeBins = 256;   // counts floor .. floor + 254, and above
 template <int NT>
 __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
+    static_assert(NT >= 64 && NT % 64 == 0, "wave 0 reads the histogram");
     __shared__ uint64_t buf[kMergeBuf];
-    __shared__ uint32_t s_cnt, s_floor;
+    __shared__ uint32_t hist[kMergeBins];
+    __shared__ uint32_t s_cnt, s_floor, s_thr, s_reached;
     if (p.qcount && blockIdx.x >= *p.qcount)
         return;
     const uint32_t q = p.qlist ? p.qlist[blockIdx.x] : blockIdx.x;
@@ -861,6 +866,8 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
         s_floor = 0;
         s_cnt = 0;
     }
+    for (uint32_t b = tid; b < kMergeBins; b += NT)
+        hist[b] = 0;
     __syncthreads();
     uint32_t fl = 0;
     for (uint32_t t = tid; t < p.n_tiles; t += NT)
@@ -868,13 +875,51 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
     atomicMax(&s_floor, fl);
     __syncthreads();
     const uint32_t floor_count = s_floor;
+    for (uint64_t i = tid; i < ncand; i += NT) {
+        const uint64_t key = cand[i];
+        const uint32_t c = (uint32_t)(key >> 32);
+        if (key != 0 && c >= floor_count)
+            atomicAdd(&hist[min(c - floor_count, (uint32_t)kMergeBins - 1u)], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        // lane l holds bins 4(63 - l) .. 4(63 - l) + 3, so the wave's
+        // inclusive sum is the number of candidates at or above each lane's
+        // lowest bin; the first lane to reach k holds the k-th count
+        const uint32_t b0 = 4u * (63u - tid);
+        const uint32_t h0 = hist[b0], h1 = hist[b0 + 1], h2 = hist[b0 + 2], h3 = hist[b0 + 3];
+        const uint32_t v = h0 + h1 + h2 + h3;
+        const uint32_t at_or_above = wave_inclusive_sum(v);
+        const uint64_t hit = __ballot(at_or_above >= k);
+        if (tid == 63)
+            s_reached = at_or_above;
+        if (hit == 0) {
+            if (tid == 0)
+                s_thr = floor_count;   // fewer than k candidates: keep them all
+        } else if (tid == (uint32_t)(__ffsll((unsigned long long)hit) - 1)) {
+            uint32_t above = at_or_above - v + h3, b = b0 + 3;
+            if (above < k) {
+                above += h2;
+                b--;
+                if (above < k) {
+                    above += h1;
+                    b--;
+                    if (above < k)
+                        b--;
+                }
+            }
+            s_thr = floor_count + b;
+        }
+    }
+    __syncthreads();
+    const uint32_t thr = s_thr;
+    const uint32_t kept = s_reached;   // candidates that reached the floor
     uint32_t kc = 0;     // valid keys at the front of buf, sorted descending
-    uint32_t kept = 0;   // candidates that reached the floor
     for (uint64_t c0 = 0; c0 < ncand; c0 += kMergeChunk) {
         const uint64_t c1 = min<uint64_t>(ncand, c0 + kMergeChunk);
         for (uint64_t i = c0 + tid; i < c1; i += NT) {
             const uint64_t key = cand[i];
-            if (key != 0 && (uint32_t)(key >> 32) >= floor_count) {
+            if (key != 0 && (uint32_t)(key >> 32) >= thr) {
                 const uint32_t pos = atomicAdd(&s_cnt, 1u);
                 buf[kc + pos] = key;
             }
@@ -887,7 +932,6 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
         __syncthreads();
         if (added == 0)
             continue;
-        kept += added;
         const uint32_t m = kc + added;
         uint32_t np2 = 1;
         while (np2 < m)
