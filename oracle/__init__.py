@@ -333,10 +333,13 @@ def exact_knn_l2(points: np.ndarray, queries: np.ndarray, k: int,
         Q = np.asarray(queries[q0:q1], dtype=np.float64)
         d2 = pn[None, :] - 2.0 * (Q @ P.T) + np.einsum("ij,ij->i", Q, Q)[:, None]
         np.maximum(d2, 0.0, out=d2)
-        part = np.argpartition(d2, k - 1, axis=1)[:, :k]
         for r in range(q1 - q0):
-            cand = part[r]
-            order = np.lexsort((cand, d2[r, cand]))
+            # every point at or below the k-th smallest distance, then the
+            # order (distance, id): points tied at the k-th distance are
+            # taken by id
+            kth = np.partition(d2[r], k - 1)[k - 1]
+            cand = np.flatnonzero(d2[r] <= kth)
+            order = np.lexsort((cand, d2[r, cand]))[:k]
             ids[q0 + r] = cand[order]
             dist[q0 + r] = np.sqrt(d2[r, cand[order]])
     return ids, dist
