@@ -199,6 +199,30 @@ int genie_search_async(const genie_index *ix, const uint64_t *d_q_offsets,
                        void *d_workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * genie_search_async with its workspace taken from a device array that the
+ * library holds instead of a caller buffer.  The array is
+ * GENIE_NOALLOC_WORKSPACE_BYTES on every GPU the library runs on, one copy
+ * per GPU, kept until the process ends; the call allocates nothing.
+ *   Arguments, results and errors as genie_search_async without the
+ *   workspace.  The index's GPU must be the current device.
+ *   Limit: genie_search_workspace_size(ix, n_queries, k) must not exceed
+ *   GENIE_NOALLOC_WORKSPACE_BYTES, else GENIE_ERANGE and nothing is
+ *   enqueued (e.g. 1,024 queries at k = 100 over 16 tiles take 13.2 MB).
+ *   Every call on one GPU shares that GPU's array, which keeps the last
+ *   call's contents (each call clears what must start at zero on its stream
+ *   before its kernels read it): calls that overlap on one GPU -- on
+ *   different streams, or from threads without ordering -- race and give
+ *   undefined results.  Order them on one stream.
+ */
+#define GENIE_NOALLOC_WORKSPACE_BYTES (64u << 20)
+int genie_search_noalloc_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                               const genie_item *d_items, uint64_t n_items, uint32_t n_queries,
+                               uint32_t max_items, uint32_t k, uint32_t *d_out_ids,
+                               uint32_t *d_out_counts, void *stream);
+
+/*
  * Search with a learned initial gate (an extension of Algorithm 1: the paper
  * starts the AuditThreshold at 1).  For each query the AuditThreshold starts
  * at max(1, floor(d_gate[q] - gate_delta)), capped at s + 1, where d_gate[q]

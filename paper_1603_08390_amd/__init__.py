@@ -47,8 +47,9 @@ EXPORTED = (
     "genie_parts_search_async", "genie_search_spq_async", "genie_rbh_signatures",
     "genie_build_index_sets", "genie_seq_build", "genie_seq_free", "genie_seq_info_get",
     "genie_seq_match_index", "genie_seq_decompose_async", "genie_seq_verify_async",
-    "genie_seq_workspace_size", "genie_seq_search_async",
+    "genie_seq_workspace_size", "genie_seq_search_async", "genie_search_noalloc_async",
 )
+NOALLOC_WORKSPACE_BYTES = 64 << 20
 GATE_FEATURES = 64
 GATE_PARAMS = 24961
 
@@ -133,6 +134,8 @@ def load() -> ctypes.CDLL:
     lib.genie_search_rows_async.restype = ctypes.c_int
     lib.genie_search_spq_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, vp, vp, sz, vp]
     lib.genie_search_spq_async.restype = ctypes.c_int
+    lib.genie_search_noalloc_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, vp, vp]
+    lib.genie_search_noalloc_async.restype = ctypes.c_int
     lib.genie_parts_build.argtypes = [vp, u64, u32, u32, u64, u32, ctypes.POINTER(vp)]
     lib.genie_parts_build.restype = ctypes.c_int
     lib.genie_parts_free.argtypes = [vp]
@@ -575,6 +578,20 @@ def genie_search_async(index: Index, d_q_offsets, d_items, k: int, max_items: in
                                      _dev_ptr(out_counts), _dev_ptr(workspace),
                                      workspace.numel(), _stream_handle(stream)))
     return out_ids, out_counts, workspace
+
+
+def genie_search_noalloc_async(index: Index, d_q_offsets, d_items, k: int, max_items: int,
+                               out_ids, out_counts, stream=None):
+    """genie_search_async with the workspace held by the library (the call
+    allocates nothing; outputs are the caller's); returns (ids, counts).
+    Calls that overlap on one GPU share that workspace and race."""
+    nq = d_q_offsets.numel() - 1
+    if nq > 0:
+        _check(load().genie_search_noalloc_async(index.handle, _dev_ptr(d_q_offsets),
+                                                 _dev_ptr(d_items), d_items.numel() // 3, nq,
+                                                 int(max_items), int(k), _dev_ptr(out_ids),
+                                                 _dev_ptr(out_counts), _stream_handle(stream)))
+    return out_ids, out_counts
 
 
 def genie_search_gated_async(index: Index, d_q_offsets, d_items, k: int, max_items: int,

@@ -531,6 +531,40 @@ extern "C" int genie_search_async(const genie_index *ix, const uint64_t *d_q_off
                          (hipStream_t)stream);
 }
 
+extern "C" int genie_search_noalloc_async(const genie_index *ix, const uint64_t *d_q_offsets,
+                                          const genie_item *d_items, uint64_t n_items,
+                                          uint32_t n_queries, uint32_t max_items, uint32_t k,
+                                          uint32_t *d_out_ids, uint32_t *d_out_counts,
+                                          void *stream) {
+    clear_error();
+    int rc = check_common(ix, n_queries, k);
+    if (rc || n_queries == 0)
+        return rc;
+    const size_t need = workspace_layout(ix, n_queries, k).total;
+    if (need > GENIE_NOALLOC_WORKSPACE_BYTES) {
+        set_error("search needs %zu bytes of workspace; the held workspace has %u "
+                  "(fewer queries per call, or genie_search_async with a caller buffer)",
+                  need, GENIE_NOALLOC_WORKSPACE_BYTES);
+        return GENIE_ERANGE;
+    }
+    int dev = -1;
+    GENIE_HIP(hipGetDevice(&dev));
+    if (dev != ix->device) {
+        set_error("index lives on device %d but device %d is current", ix->device, dev);
+        return GENIE_EINVAL;
+    }
+    void *ws = nullptr;
+    if ((rc = noalloc_workspace(dev, &ws)))
+        return rc;
+    rc = check_async(ix, d_q_offsets, d_items, n_queries, max_items, k, d_out_ids, d_out_counts,
+                     ws);
+    if (rc)
+        return rc;
+    return launch_search(ix, d_q_offsets, d_items, n_items, n_queries, max_items, k, d_out_ids,
+                         d_out_counts, nullptr, ws, GENIE_NOALLOC_WORKSPACE_BYTES,
+                         (hipStream_t)stream);
+}
+
 extern "C" int genie_search_gated_async(const genie_index *ix, const uint64_t *d_q_offsets,
                                         const genie_item *d_items, uint64_t n_items,
                                         uint32_t n_queries, uint32_t max_items, uint32_t k,

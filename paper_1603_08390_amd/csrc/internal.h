@@ -141,6 +141,11 @@ int launch_part_merge(uint64_t n_total, uint32_t tiles_total, uint32_t n_queries
                       void *d_workspace, uint32_t *d_out_ids, uint32_t *d_out_counts,
                       hipStream_t stream);
 
+// Device address of this device's held workspace of
+// GENIE_NOALLOC_WORKSPACE_BYTES (search.hip); `device` must be current on the
+// first call for it.  Allocates nothing.
+int noalloc_workspace(int device, void **out);
+
 // Opt-in kernel timing (timing.cpp): begin returns an event handle or null.
 void *timing_begin(hipStream_t st);
 void timing_end(void *start, hipStream_t st, int kind);

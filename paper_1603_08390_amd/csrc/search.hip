@@ -16,6 +16,8 @@
 // order is total.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace genie {
@@ -1217,6 +1219,48 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     fm.qcount = fb_count;
     hipLaunchKernelGGL(merge_kernel<256>, dim3(n_queries), dim3(256), 0, stream, fm);
     GENIE_HIP(hipGetLastError());
+    return GENIE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace held by the library for callers that cannot allocate device
+// memory (genie_search_noalloc_async).  Every GPU the library runs on gets
+// its own copy of this array when the code object is loaded there, at its
+// own address, and keeps it until the process ends.  In host code the
+// array's name is only a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, asked once per device with that device current.
+// ---------------------------------------------------------------------------
+namespace {
+__device__ __align__(256) uint8_t scratch[GENIE_NOALLOC_WORKSPACE_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+int noalloc_workspace(int device, void **out) {
+    if (device < 0 || device >= kMaxScratchDevices) {
+        set_error("device %d outside the %d devices the held workspace supports", device,
+                  kMaxScratchDevices);
+        return GENIE_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        GENIE_HIP(hipGetDevice(&cur));
+        if (cur != device) {
+            set_error("device %d is not current (current: %d)", device, cur);
+            return GENIE_EINVAL;
+        }
+        void *ptr = nullptr;
+        GENIE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255) != 0) {
+            set_error("held workspace has no usable device address");
+            return GENIE_EDEVICE;
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
     return GENIE_OK;
 }
 

@@ -166,3 +166,11 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_noalloc_argument_errors_without_device():
+    lib = genie.load()
+    # the held-workspace search on a null index
+    assert lib.genie_search_noalloc_async(None, None, None, 0, 4, 8, 10, None, None,
+                                          None) == genie.GENIE_EINVAL
+    assert b"null index" in lib.genie_last_error()
