@@ -144,6 +144,18 @@ int genie_index_set_scan_shape(genie_index *ix, uint32_t threads, uint32_t unrol
  */
 int genie_index_set_scan_schedule(genie_index *ix, uint32_t persistent);
 
+/*
+ * Caps the Hash Table of the count priority queue (Section 3.3.2) at
+ * 2^log2_slots slots for later searches on this index; 0 restores the
+ * default (the smallest power of two >= 4k, at least 64).  The paper sizes
+ * the table only as O(k x largest count); a tile whose table runs out of
+ * slots flags the overflow and selects its top-k from its exact counters
+ * instead, with the same answers (the statistic "tiles whose hash table
+ * overflowed" counts such tiles).  For tests of that fallback and for
+ * measurement.  log2_slots <= 16.  Errors: GENIE_EINVAL.
+ */
+int genie_index_set_hash_slots(genie_index *ix, uint32_t log2_slots);
+
 /* Describe an index.  Errors: GENIE_EINVAL. */
 int genie_index_info_get(const genie_index *ix, genie_index_info *out);
 
@@ -585,8 +597,8 @@ int genie_seq_search_async(const genie_seq_index *sx, const uint8_t *d_qchars,
 
 /*
  * Per-kernel timing for measurement.  While enabled, every search call
- * records a HIP event pair around its scan kernel and around its merge
- * kernel, on the stream of the call.  genie_kernel_timing_read waits for the
+ * records a HIP event pair around its scan kernel, around its merge kernel
+ * and (gated search) around its fallback scan, on the stream of the call.  genie_kernel_timing_read waits for the
  * recorded events, adds up their elapsed times and (if reset != 0) clears the
  * totals.  Disabled by default; process-wide; thread-safe.
  */
@@ -595,10 +607,38 @@ typedef struct {
     double scan_ms;      /* summed event time of the scan + c-PQ kernel */
     uint64_t merge_launches;
     double merge_ms;     /* summed event time of the per-query merge kernel */
+    uint64_t fallback_launches;
+    double fallback_ms;  /* summed event time of the gated search's fallback scan */
 } genie_kernel_times;
 
 int genie_kernel_timing_enable(int on);
 int genie_kernel_timing_read(genie_kernel_times *out, int reset);
+
+/*
+ * Measurement probes (not part of the search): the peak rates the search
+ * kernels are priced against, measured on the current device.  Both run on
+ * the null stream and wait for their own kernels.
+ *
+ * genie_probe_lds_atomics: n_blocks workgroups of 1024 threads, 64 KB of LDS
+ * each (two share a CU, as the scan kernel's at 8-bit counters), every lane
+ * issuing steps x 8 32-bit LDS atomic adds, 8 independent ones at a time.
+ *   mode 0: with return, lane-consecutive words (no bank conflicts);
+ *   mode 1: with return, pseudo-random words of the 64 KB;
+ *   mode 2: without return, pseudo-random words.
+ *   d_sink: device, n_blocks * 1024 uint32 (written; keeps results live).
+ *   *out_per_s: atomic adds per second over the chip (one untimed launch,
+ *   then one timed by HIP events).
+ * genie_probe_hbm: a streaming read of `bytes` at d_src (16-byte loads,
+ * grid-stride), `reps` launches timed together -> *out_read_gbs; with d_dst
+ * set, a copy of d_src into d_dst likewise -> *out_copy_gbs (bytes read plus
+ * bytes written).  bytes: a multiple of 16, well above the 256 MB of
+ * Infinity Cache for an HBM figure.  d_sink: device, >= 1 uint32.
+ * Errors: GENIE_EINVAL (bad arguments), GENIE_EDEVICE.
+ */
+int genie_probe_lds_atomics(int mode, uint32_t steps, uint32_t n_blocks, uint32_t *d_sink,
+                            double *out_per_s);
+int genie_probe_hbm(const void *d_src, void *d_dst, uint64_t bytes, uint32_t reps,
+                    uint32_t *d_sink, double *out_read_gbs, double *out_copy_gbs);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *genie_last_error(void);

@@ -19,7 +19,7 @@ from typing import Optional, Tuple
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.environ.get("GENIE_LIB", os.path.join(HERE, "libgenie.so"))
+LIB_PATH = os.path.join(HERE, "libgenie.so")
 
 GENIE_OK = 0
 GENIE_EINVAL = -22
@@ -48,6 +48,7 @@ EXPORTED = (
     "genie_build_index_sets", "genie_seq_build", "genie_seq_free", "genie_seq_info_get",
     "genie_seq_match_index", "genie_seq_decompose_async", "genie_seq_verify_async",
     "genie_seq_workspace_size", "genie_seq_search_async", "genie_search_noalloc_async",
+    "genie_probe_lds_atomics", "genie_probe_hbm", "genie_index_set_hash_slots",
 )
 NOALLOC_WORKSPACE_BYTES = 64 << 20
 GATE_FEATURES = 64
@@ -62,7 +63,8 @@ class GenieError(RuntimeError):
 
 class _KernelTimes(ctypes.Structure):
     _fields_ = [("scan_launches", ctypes.c_uint64), ("scan_ms", ctypes.c_double),
-                ("merge_launches", ctypes.c_uint64), ("merge_ms", ctypes.c_double)]
+                ("merge_launches", ctypes.c_uint64), ("merge_ms", ctypes.c_double),
+                ("fallback_launches", ctypes.c_uint64), ("fallback_ms", ctypes.c_double)]
 
 
 class _PartsInfo(ctypes.Structure):
@@ -136,6 +138,11 @@ def load() -> ctypes.CDLL:
     lib.genie_search_spq_async.restype = ctypes.c_int
     lib.genie_search_noalloc_async.argtypes = [vp, vp, vp, u64, u32, u32, u32, vp, vp, vp]
     lib.genie_search_noalloc_async.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.genie_probe_lds_atomics.argtypes = [ctypes.c_int, u32, u32, vp, dp]
+    lib.genie_probe_lds_atomics.restype = ctypes.c_int
+    lib.genie_probe_hbm.argtypes = [vp, vp, u64, u32, vp, dp, dp]
+    lib.genie_probe_hbm.restype = ctypes.c_int
     lib.genie_parts_build.argtypes = [vp, u64, u32, u32, u64, u32, ctypes.POINTER(vp)]
     lib.genie_parts_build.restype = ctypes.c_int
     lib.genie_parts_free.argtypes = [vp]
@@ -162,6 +169,8 @@ def load() -> ctypes.CDLL:
     lib.genie_index_set_scan_shape.restype = ctypes.c_int
     lib.genie_index_set_scan_schedule.argtypes = [vp, u32]
     lib.genie_index_set_scan_schedule.restype = ctypes.c_int
+    lib.genie_index_set_hash_slots.argtypes = [vp, u32]
+    lib.genie_index_set_hash_slots.restype = ctypes.c_int
     lib.genie_build_index_sets.argtypes = [vp, vp, u64, u32, u32, ctypes.POINTER(vp)]
     lib.genie_build_index_sets.restype = ctypes.c_int
     lib.genie_seq_build.argtypes = [vp, vp, u64, u32, u32, ctypes.POINTER(vp)]
@@ -530,6 +539,11 @@ SCAN_SHAPES = ((512, 4), (512, 8), (1024, 4), (1024, 8))
 SCAN_SCHEDULES = (0, 1)   # one workgroup per pair, persistent
 
 
+def genie_index_set_hash_slots(index: Index, log2_slots: int):
+    """Cap the c-PQ Hash Table at 2^log2_slots slots (0: default size)."""
+    _check(load().genie_index_set_hash_slots(index.handle, int(log2_slots)))
+
+
 def genie_search(index: Index, q_offsets: np.ndarray, items: np.ndarray, k: int
                  ) -> Tuple[np.ndarray, np.ndarray]:
     """Synchronous search with host arrays; returns (ids, counts) [nq, k] uint32."""
@@ -779,6 +793,30 @@ def genie_rbh_signatures(d_points, d_g, d_u, d_seeds, log2_buckets: int, out=Non
     return out
 
 
+def genie_probe_lds_atomics(mode: int, steps: int = 4096, n_blocks: int = 4096) -> float:
+    """LDS atomic adds per second over the chip (mode 0: with return,
+    conflict-free; 1: with return, random words; 2: without return, random)."""
+    import torch
+    sink = torch.empty(n_blocks * 1024, dtype=torch.int32, device="cuda")
+    out = ctypes.c_double()
+    _check(load().genie_probe_lds_atomics(int(mode), int(steps), int(n_blocks), _dev_ptr(sink),
+                                          ctypes.byref(out)))
+    return out.value
+
+
+def genie_probe_hbm(nbytes: int = 2 << 30, reps: int = 5) -> Tuple[float, float]:
+    """Streaming read and copy rates in GB/s over two device buffers of nbytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    rd, cp = ctypes.c_double(), ctypes.c_double()
+    _check(load().genie_probe_hbm(_dev_ptr(src), _dev_ptr(dst), src.numel() * 4, int(reps),
+                                  _dev_ptr(sink), ctypes.byref(rd), ctypes.byref(cp)))
+    del src, dst
+    return rd.value, cp.value
+
+
 def genie_kernel_timing_enable(on: bool = True):
     _check(load().genie_kernel_timing_enable(1 if on else 0))
 
@@ -787,7 +825,8 @@ def genie_kernel_timing_read(reset: bool = True) -> dict:
     t = _KernelTimes()
     _check(load().genie_kernel_timing_read(ctypes.byref(t), 1 if reset else 0))
     return {"scan_launches": t.scan_launches, "scan_ms": t.scan_ms,
-            "merge_launches": t.merge_launches, "merge_ms": t.merge_ms}
+            "merge_launches": t.merge_launches, "merge_ms": t.merge_ms,
+            "fallback_launches": t.fallback_launches, "fallback_ms": t.fallback_ms}
 
 
 def genie_lsh_items_async(d_sig, out=None, stream=None):

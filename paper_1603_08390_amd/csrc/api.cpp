@@ -45,13 +45,14 @@ WorkspaceLayout workspace_layout_tiles(uint64_t n_tiles, uint32_t n_queries, uin
     L.status = 0;
     L.tile_kth = 256;
     L.cand = align256(L.tile_kth + pairs * sizeof(uint32_t));
-    L.fb_list = align256(L.cand + pairs * (uint64_t)k * sizeof(uint64_t));
+    L.pair_stats = align256(L.cand + pairs * (uint64_t)k * sizeof(uint64_t));
+    L.fb_list = align256(L.pair_stats + pairs * 4 * sizeof(uint32_t));
     L.total = align256(L.fb_list + (uint64_t)n_queries * sizeof(uint32_t));
     return L;
 }
 
 int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2,
-                 SearchShape *out) {
+                 SearchShape *out, uint32_t ht_log2_cap) {
     // Counter width b: counts reach at most max_items; one more code (all
     // ones) marks an object already emitted during selection.
     static const int widths[] = {4, 8, 16};
@@ -70,6 +71,8 @@ int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2
     uint32_t lg = 6;
     while ((1u << lg) < 4u * k)
         lg++;
+    if (ht_log2_cap)   // a smaller table set on the index (overflow handling, tests)
+        lg = std::min(lg, ht_log2_cap);
     const uint32_t cpw = 32 / bits;
     // static part: the Bitmap Counter (a counter for every local id and the
     // padding id) and one word of the persistent schedule
@@ -165,7 +168,9 @@ static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nk
                 row[key + 1] = (uint32_t)off;
                 prow[key + 1] = pads;
             }
-            if (off + 2 * kSentinelDwords >= 0xFFFFFFFFull)
+            // the scan addresses a tile's postings by a 32-bit byte offset
+            // (2 bytes per element): fewer than 2^31 elements per tile
+            if (off + 2 * kSentinelDwords >= (1ull << 31))
                 overflow.store(1);
             tile_size[t] = off + 2 * kSentinelDwords;   // trailing all-sentinel dwords
         }
@@ -189,7 +194,7 @@ static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nk
         return GENIE_EINVAL;
     }
     if (overflow.load()) {
-        set_error("a tile holds too many postings for 32-bit tile offsets");
+        set_error("a tile holds 2^31 or more postings (32-bit byte offsets in the scan)");
         return GENIE_EINVAL;
     }
     tile_base[0] = 0;
@@ -433,6 +438,16 @@ extern "C" int genie_index_set_scan_schedule(genie_index *ix, uint32_t persisten
         return GENIE_EINVAL;
     }
     ix->scan_persistent = (int)persistent;
+    return GENIE_OK;
+}
+
+extern "C" int genie_index_set_hash_slots(genie_index *ix, uint32_t log2_slots) {
+    clear_error();
+    if (!ix || log2_slots > 16) {
+        set_error("hash table slots must be 2^1 .. 2^16, or 0 for the default");
+        return GENIE_EINVAL;
+    }
+    ix->ht_log2_cap = log2_slots;
     return GENIE_OK;
 }
 

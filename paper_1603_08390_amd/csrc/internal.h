@@ -54,6 +54,7 @@ struct genie_index {
     int scan_threads = kScanThreadsDefault;   // launch shape of the scan kernel
     int scan_unroll = kScanUnrollDefault;
     int scan_persistent = 0;                  // 1: persistent workgroups over a pair queue
+    uint32_t ht_log2_cap = 0;                 // Hash Table slots capped at 2^cap (0: no cap)
     bool key_sets = false;                    // built from keyword sets: d = 1, V = keywords
 };
 
@@ -96,6 +97,8 @@ struct WorkspaceLayout {
     size_t status = 0;     // uint32 flags + pad, uint64 stats[4], uint32 fallback count
     size_t tile_kth = 0;   // uint32 [n_queries * n_tiles]
     size_t cand = 0;       // uint64 [n_queries * n_tiles * k]
+    size_t pair_stats = 0; // uint32 x 4 [n_queries * n_tiles]: postings scanned, hash-table
+                           // overflow (0/1), insertions, gate passes of each pair
     size_t fb_list = 0;    // uint32 [n_queries] (gated search)
     size_t total = 0;
 };
@@ -111,7 +114,7 @@ struct SearchShape {
     size_t lds_bytes = 0;  // dynamic LDS of the scan kernel (the counters are static)
 };
 int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2,
-                 SearchShape *out);
+                 SearchShape *out, uint32_t ht_log2_cap = 0);
 
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,

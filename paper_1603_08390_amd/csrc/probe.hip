@@ -1,0 +1,179 @@
+// Measurement probes: the rates that the search kernels' rooflines are
+// priced against, measured on the device the library runs on.  Not part of
+// the search path.
+//
+//  * LDS atomic add rate: workgroups of 1024 threads with 64 KB of LDS each
+//    (two per CU, the occupancy of the scan kernel at 8-bit counters), every
+//    lane issuing 32-bit LDS atomic adds in groups of 8 independent ones, as
+//    the scan's counting loop does.  Modes: returning adds at lane-consecutive
+//    words (conflict-free), returning adds at pseudo-random words of the 64 KB,
+//    and non-returning adds at pseudo-random words.
+//  * HBM streaming rate: a read of a device buffer (16-byte loads, coalesced,
+//    grid-stride) and a copy into a second buffer.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace genie {
+namespace {
+
+constexpr int kProbeThreads = 1024;
+constexpr uint32_t kProbeWords = 16384;   // 64 KB of LDS
+constexpr int kProbeBatch = 8;            // independent atomics per lane and step
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // one 16-byte load
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // a bijective integer mixer (xorshift-multiply), for scattered addresses
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kProbeThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void lds_atomic_probe_kernel(uint32_t steps, uint32_t *sink) {
+    __shared__ uint32_t buf[kProbeWords];
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < kProbeWords; i += kProbeThreads)
+        buf[i] = 0;
+    __syncthreads();
+    uint32_t acc = 0;
+    uint32_t seed = mix32(blockIdx.x * kProbeThreads + tid);
+    for (uint32_t s = 0; s < steps; s++) {
+        uint32_t addr[kProbeBatch];
+#pragma unroll
+        for (int j = 0; j < kProbeBatch; j++) {
+            if (MODE == 0)   // wave w, lane l: word 64 w + l of a 1024-word block
+                addr[j] = (tid + (uint32_t)j * kProbeThreads + s * 128u) & (kProbeWords - 1);
+            else
+                addr[j] = mix32(seed + (uint32_t)j * 0x9e3779b9u) & (kProbeWords - 1);
+        }
+        seed += 0x632be5abu;
+        if (MODE == 2) {
+#pragma unroll
+            for (int j = 0; j < kProbeBatch; j++)
+                __hip_atomic_fetch_add(&buf[addr[j]], 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            uint32_t r[kProbeBatch];
+#pragma unroll
+            for (int j = 0; j < kProbeBatch; j++)
+                r[j] = __hip_atomic_fetch_add(&buf[addr[j]], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+            for (int j = 0; j < kProbeBatch; j++)
+                acc += r[j];
+        }
+    }
+    __syncthreads();
+    if (MODE == 2)
+        acc = buf[tid];
+    sink[blockIdx.x * kProbeThreads + tid] = acc;
+}
+
+__global__ __launch_bounds__(256) void hbm_read_kernel(const u32x4 *src, uint64_t n16, uint32_t *sink) {
+    uint32_t acc = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
+        const u32x4 v = __builtin_nontemporal_load(src + i);
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    if (acc == 0x9e3779b9u)   // practically never: keeps the loads live
+        sink[0] = acc;
+}
+
+__global__ __launch_bounds__(256) void hbm_copy_kernel(const u32x4 *src, u32x4 *dst, uint64_t n16) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a)
+            (void)hipEventDestroy(a);
+        if (b)
+            (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+}  // namespace genie
+
+using namespace genie;
+
+extern "C" int genie_probe_lds_atomics(int mode, uint32_t steps, uint32_t n_blocks,
+                                       uint32_t *d_sink, double *out_per_s) {
+    clear_error();
+    if (!d_sink || !out_per_s || mode < 0 || mode > 2 || steps == 0 || n_blocks == 0) {
+        set_error("bad probe arguments");
+        return GENIE_EINVAL;
+    }
+    const void *kern = mode == 0 ? (const void *)lds_atomic_probe_kernel<0>
+                     : mode == 1 ? (const void *)lds_atomic_probe_kernel<1>
+                                 : (const void *)lds_atomic_probe_kernel<2>;
+    EventPair ev;
+    GENIE_HIP(hipEventCreate(&ev.a));
+    GENIE_HIP(hipEventCreate(&ev.b));
+    void *args[] = {&steps, &d_sink};
+    // one untimed launch (code load, clocks), then the timed one
+    GENIE_HIP(hipLaunchKernel(kern, dim3(n_blocks), dim3(kProbeThreads), args, 0, nullptr));
+    GENIE_HIP(hipEventRecord(ev.a, nullptr));
+    GENIE_HIP(hipLaunchKernel(kern, dim3(n_blocks), dim3(kProbeThreads), args, 0, nullptr));
+    GENIE_HIP(hipEventRecord(ev.b, nullptr));
+    GENIE_HIP(hipEventSynchronize(ev.b));
+    float ms = 0.0f;
+    GENIE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    const double ops = (double)n_blocks * kProbeThreads * steps * kProbeBatch;
+    *out_per_s = ms > 0.0f ? ops / (ms * 1e-3) : 0.0;
+    return GENIE_OK;
+}
+
+extern "C" int genie_probe_hbm(const void *d_src, void *d_dst, uint64_t bytes, uint32_t reps,
+                               uint32_t *d_sink, double *out_read_gbs, double *out_copy_gbs) {
+    clear_error();
+    if (!d_src || !d_sink || !out_read_gbs || bytes < 16 || (bytes & 15) || reps == 0 ||
+        ((uintptr_t)d_src & 15) || (d_dst && ((uintptr_t)d_dst & 15))) {
+        set_error("bad probe arguments");
+        return GENIE_EINVAL;
+    }
+    int dev = 0, cus = 0;
+    GENIE_HIP(hipGetDevice(&dev));
+    GENIE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const uint64_t n16 = bytes / 16;
+    const uint32_t grid = (uint32_t)std::max(1, cus) * 16;
+    const u32x4 *src = static_cast<const u32x4 *>(d_src);
+    EventPair ev;
+    GENIE_HIP(hipEventCreate(&ev.a));
+    GENIE_HIP(hipEventCreate(&ev.b));
+    float ms = 0.0f;
+    hipLaunchKernelGGL(hbm_read_kernel, dim3(grid), dim3(256), 0, nullptr, src, n16, d_sink);
+    GENIE_HIP(hipEventRecord(ev.a, nullptr));
+    for (uint32_t r = 0; r < reps; r++)
+        hipLaunchKernelGGL(hbm_read_kernel, dim3(grid), dim3(256), 0, nullptr, src, n16, d_sink);
+    GENIE_HIP(hipEventRecord(ev.b, nullptr));
+    GENIE_HIP(hipEventSynchronize(ev.b));
+    GENIE_HIP(hipGetLastError());
+    GENIE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    *out_read_gbs = ms > 0.0f ? (double)bytes * reps / (ms * 1e-3) / 1e9 : 0.0;
+    if (d_dst && out_copy_gbs) {
+        u32x4 *dst = static_cast<u32x4 *>(d_dst);
+        hipLaunchKernelGGL(hbm_copy_kernel, dim3(grid), dim3(256), 0, nullptr, src, dst, n16);
+        GENIE_HIP(hipEventRecord(ev.a, nullptr));
+        for (uint32_t r = 0; r < reps; r++)
+            hipLaunchKernelGGL(hbm_copy_kernel, dim3(grid), dim3(256), 0, nullptr, src, dst, n16);
+        GENIE_HIP(hipEventRecord(ev.b, nullptr));
+        GENIE_HIP(hipEventSynchronize(ev.b));
+        GENIE_HIP(hipGetLastError());
+        GENIE_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+        // bytes moved over HBM: read once and written once
+        *out_copy_gbs = ms > 0.0f ? 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9 : 0.0;
+    }
+    return GENIE_OK;
+}

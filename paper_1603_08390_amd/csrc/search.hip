@@ -37,6 +37,8 @@ struct ScanParams {
     uint64_t per_xcd;       // (query, tile) pairs handled per XCD slice
     uint64_t *cand;         // [nq][n_tiles][k] packed keys
     uint32_t *tile_kth;     // [nq][n_tiles]
+    uint4 *pair_stats;      // [nq][n_tiles] statistics of each pair, or null (count dump:
+                            // added to the status block directly)
     uint32_t *full_counts;  // [nq][n] (count dump mode) or null
     uint32_t *status;       // flags word; stats as uint64 at status + 2
     const float *gate;      // predicted k-th count per query (gated search) or null
@@ -64,6 +66,8 @@ enum : int { kSchedGrid = 0, kSchedQueue = 1, kSchedRows = 2 };
 struct MergeParams {
     const uint64_t *cand;
     const uint32_t *tile_kth;
+    const uint4 *pair_stats;  // per-pair statistics, summed per query into the status block
+    uint32_t *status;
     uint64_t n;
     uint32_t n_tiles, k;
     uint32_t *out_ids, *out_counts;
@@ -295,7 +299,6 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                                           uint32_t *smem) {
     static_assert(BITS == 4 || BITS == 8 || BITS == 16, "power-of-two counter width");
     constexpr uint32_t CPW = 32 / BITS;                   // counters per word
-    constexpr uint32_t LCPW = BITS == 4 ? 3 : (BITS == 8 ? 2 : 1);   // log2(CPW)
     constexpr uint32_t LBITS = BITS == 4 ? 2 : (BITS == 8 ? 3 : 4);  // log2(BITS)
     constexpr uint32_t MASK = (1u << BITS) - 1;           // also the "emitted" mark
     constexpr uint32_t TILE = (1u << LG) - 1;             // objects per tile
@@ -435,8 +438,10 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         } else {
             for (uint32_t i = tid; i < p.k; i += NT)
                 p.cand[row * p.k + i] = 0;
-            if (tid == 0)
+            if (tid == 0) {
                 p.tile_kth[row] = 0;
+                p.pair_stats[row] = make_uint4(0u, 0u, 0u, 0u);
+            }
         }
         return;
     }
@@ -667,13 +672,20 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     if constexpr (SPQ)
         AT = spq_thr + 1;
     if (tid == 0) {
-        const uint64_t scanned = misc[M_SCANNED];
-        unsigned long long *stats = reinterpret_cast<unsigned long long *>(p.status + 2);
-        atomicAdd(&stats[0], (unsigned long long)scanned);
-        if (from_counters && !SPQ)
-            atomicAdd(&stats[1], 1ull);
-        atomicAdd(&stats[2], (unsigned long long)misc[M_INSERTS]);
-        atomicAdd(&stats[3], (unsigned long long)misc[M_PASSES]);
+        // the pair's statistics: a plain store, summed per query by the merge
+        // (one device-scope atomic per pair and counter serialises across
+        // the chip); the count dump has no merge and adds them here
+        const uint32_t scanned = misc[M_SCANNED], ovf = (from_counters && !SPQ) ? 1u : 0u;
+        if (p.pair_stats) {
+            p.pair_stats[row] = make_uint4(scanned, ovf, misc[M_INSERTS], misc[M_PASSES]);
+        } else {
+            unsigned long long *stats = reinterpret_cast<unsigned long long *>(p.status + 2);
+            atomicAdd(&stats[0], (unsigned long long)scanned);
+            if (ovf)
+                atomicAdd(&stats[1], 1ull);
+            atomicAdd(&stats[2], (unsigned long long)misc[M_INSERTS]);
+            atomicAdd(&stats[3], (unsigned long long)misc[M_PASSES]);
+        }
     }
 
     if (DUMP) {
@@ -858,6 +870,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
     __shared__ uint64_t buf[kMergeBuf];
     __shared__ uint32_t hist[kMergeBins];
     __shared__ uint32_t s_cnt, s_floor, s_thr, s_reached;
+    __shared__ unsigned long long s_stats[4];
     if (p.qcount && blockIdx.x >= *p.qcount)
         return;
     const uint32_t q = p.qlist ? p.qlist[blockIdx.x] : blockIdx.x;
@@ -868,14 +881,33 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
         s_floor = 0;
         s_cnt = 0;
     }
+    if (tid < 4)
+        s_stats[tid] = 0;
     for (uint32_t b = tid; b < kMergeBins; b += NT)
         hist[b] = 0;
     __syncthreads();
     uint32_t fl = 0;
-    for (uint32_t t = tid; t < p.n_tiles; t += NT)
+    unsigned long long st0 = 0, st1 = 0, st2 = 0, st3 = 0;
+    for (uint32_t t = tid; t < p.n_tiles; t += NT) {
         fl = max(fl, p.tile_kth[(uint64_t)q * p.n_tiles + t]);
+        const uint4 v = p.pair_stats[(uint64_t)q * p.n_tiles + t];
+        st0 += v.x;
+        st1 += v.y;
+        st2 += v.z;
+        st3 += v.w;
+    }
     atomicMax(&s_floor, fl);
+    if (st0 | st1 | st2 | st3) {
+        atomicAdd(&s_stats[0], st0);
+        atomicAdd(&s_stats[1], st1);
+        atomicAdd(&s_stats[2], st2);
+        atomicAdd(&s_stats[3], st3);
+    }
     __syncthreads();
+    if (tid < 4 && s_stats[tid]) {   // the query's statistics into the status block
+        unsigned long long *stats = reinterpret_cast<unsigned long long *>(p.status + 2);
+        atomicAdd(&stats[tid], s_stats[tid]);
+    }
     const uint32_t floor_count = s_floor;
     for (uint64_t i = tid; i < ncand; i += NT) {
         const uint64_t key = cand[i];
@@ -1010,7 +1042,7 @@ int launch_scan(const ScanParams &sp, bool dump, size_t lds, uint64_t grid, hipS
     void *args[] = {&arg};
     void *ev = timing_begin(st);
     GENIE_HIP(hipLaunchKernel(kern, dim3((uint32_t)grid), dim3(nt), args, lds, st));
-    timing_end(ev, st, 0);
+    timing_end(ev, st, sp.rows_loop ? 2 : 0);   // the row schedule is the fallback pass
     GENIE_HIP(hipGetLastError());
     return GENIE_OK;
 }
@@ -1088,6 +1120,7 @@ int launch_part_scan(const IndexView &v, uint64_t id_base, uint32_t tile_off,
     sp.per_xcd = (pairs + 7) / 8;
     sp.cand = reinterpret_cast<uint64_t *>(ws + L.cand);
     sp.tile_kth = reinterpret_cast<uint32_t *>(ws + L.tile_kth);
+    sp.pair_stats = reinterpret_cast<uint4 *>(ws + L.pair_stats);
     sp.status = reinterpret_cast<uint32_t *>(ws + L.status);
     const uint64_t grid = sp.per_xcd * 8;
     if (grid > 0x7FFFFFFFull) {
@@ -1106,6 +1139,8 @@ int launch_part_merge(uint64_t n_total, uint32_t tiles_total, uint32_t n_queries
     MergeParams mp{};
     mp.cand = reinterpret_cast<uint64_t *>(ws + L.cand);
     mp.tile_kth = reinterpret_cast<uint32_t *>(ws + L.tile_kth);
+    mp.pair_stats = reinterpret_cast<const uint4 *>(ws + L.pair_stats);
+    mp.status = reinterpret_cast<uint32_t *>(ws + L.status);
     mp.n = n_total;
     mp.n_tiles = tiles_total;
     mp.k = k;
@@ -1133,7 +1168,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     SearchShape shape;
     // the count dump and the GEN-SPQ ablation run 1024 x 4
     const int threads = (dump || spq) ? 1024 : ix->scan_threads;
-    int rc = search_shape(max_items, k, threads, ix->tile_log2, &shape);
+    int rc = search_shape(max_items, k, threads, ix->tile_log2, &shape, ix->ht_log2_cap);
     if (rc)
         return rc;
     char *ws = static_cast<char *>(d_workspace);
@@ -1161,6 +1196,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.per_xcd = (pairs + 7) / 8;
     sp.cand = reinterpret_cast<uint64_t *>(ws + L.cand);
     sp.tile_kth = reinterpret_cast<uint32_t *>(ws + L.tile_kth);
+    sp.pair_stats = dump ? nullptr : reinterpret_cast<uint4 *>(ws + L.pair_stats);
     sp.full_counts = d_full_counts;
     sp.status = reinterpret_cast<uint32_t *>(ws + L.status);
     sp.gate = d_gate;
@@ -1182,6 +1218,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     MergeParams mp{};
     mp.cand = sp.cand;
     mp.tile_kth = sp.tile_kth;
+    mp.pair_stats = sp.pair_stats;
+    mp.status = sp.status;
     mp.n = ix->n;
     mp.n_tiles = ix->n_tiles;
     mp.k = k;

@@ -12,7 +12,7 @@ namespace {
 
 struct Pending {
     hipEvent_t start, stop;
-    int kind;  // 0 scan, 1 merge
+    int kind;  // 0 scan, 1 merge, 2 fallback scan
 };
 
 std::mutex g_mu;
@@ -94,9 +94,12 @@ extern "C" int genie_kernel_timing_read(genie_kernel_times *out, int reset) {
         if (p.kind == 0) {
             g_totals.scan_launches++;
             g_totals.scan_ms += ms;
-        } else {
+        } else if (p.kind == 1) {
             g_totals.merge_launches++;
             g_totals.merge_ms += ms;
+        } else {
+            g_totals.fallback_launches++;
+            g_totals.fallback_ms += ms;
         }
         g_free.push_back(p.start);
         g_free.push_back(p.stop);

@@ -174,3 +174,20 @@ def test_noalloc_argument_errors_without_device():
     assert lib.genie_search_noalloc_async(None, None, None, 0, 4, 8, 10, None, None,
                                           None) == genie.GENIE_EINVAL
     assert b"null index" in lib.genie_last_error()
+
+
+def test_probe_argument_errors_without_device():
+    lib = genie.load()
+    # probes: bad mode, zero sizes, null outputs
+    out = ctypes.c_double()
+    assert lib.genie_probe_lds_atomics(3, 1, 1, None, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert lib.genie_probe_lds_atomics(0, 0, 1, None, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert lib.genie_probe_hbm(None, None, 1 << 20, 1, None, ctypes.byref(out),
+                               None) == genie.GENIE_EINVAL
+    assert lib.genie_probe_hbm(None, None, 15, 1, None, None, None) == genie.GENIE_EINVAL
+
+
+def test_hash_slots_argument_errors_without_device():
+    lib = genie.load()
+    assert lib.genie_index_set_hash_slots(None, 4) == genie.GENIE_EINVAL
+    assert b"hash table slots" in lib.genie_last_error()

@@ -51,6 +51,26 @@ def _check(values, V, queries, k, ix=None, qs=None, tile_log2=16):
     return st
 
 
+def oracle_rows(values, V, queries, k, threads=16, chunk=16):
+    """The oracle's answers to every query, chunks of queries on host threads
+    (its C search releases the interpreter lock); returns ids, counts and the
+    postings scanned per query."""
+    import concurrent.futures as cf
+    idx = oracle.build_csr(values, V)
+    nq = queries.n_queries
+    ids = np.zeros((nq, k), np.uint32)
+    cts = np.zeros((nq, k), np.uint32)
+    scanned = np.zeros(nq, np.uint64)
+
+    def run(q0):
+        q1 = min(nq, q0 + chunk)
+        ids[q0:q1], cts[q0:q1], _, scanned[q0:q1] = oracle.search_idx(idx, queries, k, q0, q1)
+
+    with cf.ThreadPoolExecutor(threads) as pool:
+        list(pool.map(run, range(0, nq, chunk)))
+    return ids, cts, scanned
+
+
 def test_tiny_workload_full():
     inst = workloads.tiny()
     print("tiny", inst.n, inst.d, inst.queries.n_queries, flush=True)
@@ -217,20 +237,48 @@ def test_sync_host_entry_point_and_errors():
     ix.free()
 
 
-def test_relational_full_size_sampled():
+def test_relational_full_size_every_row():
     """1,000,000 x 32, Zipf(1.1) over 256 buckets, 1,024 queries, k = 100: the
-    whole batch in one call (the benchmark's launch), 48 rows checked."""
+    whole batch in one call (the benchmark's launch: tiles of 65,535 objects,
+    1024 x 4, one workgroup per pair), every row against the oracle."""
     inst = workloads.relational()
     print("relational full", inst.n, inst.d, inst.queries.n_queries, flush=True)
     ix = genie.Index(inst.values, inst.V)
-    rng = np.random.default_rng(99)
-    qs = sorted(rng.choice(inst.queries.n_queries, size=48, replace=False).tolist())
-    qs = sorted(set(qs + [0, inst.queries.n_queries - 1]))
-    st = _check(inst.values, inst.V, inst.queries, inst.k, ix=ix, qs=qs)
+    assert ix.info.scan_shape == (1024, 4) and ix.info.scan_persistent == 0
+    ids, cts, st = _run(ix, inst.queries, inst.k)
+    assert st["status"] == 0, st
+    o_ids, o_cts, scanned = oracle_rows(inst.values, inst.V, inst.queries, inst.k)
+    assert st["postings_scanned"] == int(scanned.sum())
+    bad = np.nonzero((ids != o_ids).any(axis=1) | (cts != o_cts).any(axis=1))[0]
+    assert len(bad) == 0, f"{len(bad)} of 1024 rows differ, first {bad[0]}"
     print("stats", st, flush=True)
     ix.free()
 
 
+def test_merge_capped_histogram_bin():
+    """The merge's count histogram spans 255 counts above the largest tile
+    k-th count and pools larger counts in its top bin.  Four tiles, each with
+    25 objects matching all 400 items of the query (count 400) and every
+    other object matching none (tile k-th count 0), k = 100: the global k-th
+    count (400) lies far past the top bin."""
+    n = 4 * 65535
+    values = np.zeros((n, 4), np.uint32)
+    rng = np.random.default_rng(77)
+    special = np.concatenate([t * 65535 + rng.choice(65535, 25, replace=False)
+                              for t in range(4)])
+    values[special] = 1
+    # 40 more objects per tile hold value 1 on dim 0 only: count 100 in the
+    # first query; in the second (400 items on dim 0) they tie at 400 with
+    # the 100 above, and the 100 smallest of the 260 ids win
+    mid = np.concatenate([t * 65535 + rng.choice(np.setdiff1d(np.arange(65535),
+                                                              special % 65535), 40,
+                                                 replace=False) for t in range(4)])
+    values[mid, 0] = 1
+    items = np.array([[j % 4, 1, 1] for j in range(400)], np.uint32)
+    dim0 = np.array([[0, 1, 1]] * 400, np.uint32)
+    q = workloads.Queries(np.array([0, 400, 800], np.uint64), np.concatenate([items, dim0]))
+    print("capped merge bin:", n, "objects, 400 items, k = 100", flush=True)
+    _check(values, 2, q, 100)
 def test_lsh_signatures_vs_float64():
     inp = workloads.ann(n=100_000, nq=16)
     P = torch.from_numpy(inp.points).cuda()
