@@ -86,6 +86,16 @@ class GpuExecutor:
         ws = genie_search_workspace_size(r.index, nq, k)
         return ws + 2 * nq * k * 4 + s_total * 12 + (nq + 1) * 8 + nq * 64 * 4 + 4096
 
+    def new_held_bytes(self, slot: int, group: List[Request]) -> int:
+        """Device bytes that launching this group on this slot allocates and
+        keeps for good (none: every buffer of an eager launch is released
+        with the group)."""
+        return 0
+
+    def held_bytes(self) -> int:
+        """Device bytes the executor keeps between groups."""
+        return 0
+
     def launch(self, slot: int, group: List[Request]):
         torch = self.torch
         st = self.streams[slot]
@@ -158,6 +168,35 @@ class GraphExecutor(GpuExecutor):
         self.capacity = capacity
         self.plans = {}
 
+    def _plan_bytes(self, target: str, k: int) -> int:
+        """Device bytes of one plan at the group capacity (what _plan keeps)."""
+        r, cap = self.res[target], self.capacity
+        gated = self.use_gate and r.gate is not None
+        if r.lsh is not None:
+            m, dim = r.lsh["a"].shape[0], r.lsh["a"].shape[1]
+            inputs = cap * dim * 4 + cap * m * 4 + cap * m * 12
+        else:
+            inputs = cap * max(1, r.max_items) * 12
+        return (genie_search_workspace_size(r.index, cap, k) + 2 * cap * k * 4 + inputs +
+                (cap + 1) * 8 + 4 + (cap * 64 * 4 + cap * 4 if gated else 0))
+
+    def need_bytes(self, group: List[Request]) -> int:
+        """A group runs in its plan's buffers: nothing beyond the plan."""
+        return 0
+
+    def new_held_bytes(self, slot: int, group: List[Request]) -> int:
+        """The plan of (slot, index, k) is made on first use and kept."""
+        key = (slot, group[0].target, group[0].k)
+        return 0 if key in self.plans else self._plan_bytes(group[0].target, group[0].k)
+
+    def held_bytes(self) -> int:
+        return sum(P.bytes for P in self.plans.values())
+
+    def release_held(self):
+        """Drop every plan (only called while no group runs); they are made
+        again on next use."""
+        self.plans.clear()
+
     def _plan(self, slot: int, target: str, k: int) -> _Plan:
         key = (slot, target, k)
         if key in self.plans:
@@ -213,8 +252,7 @@ class GraphExecutor(GpuExecutor):
         with torch.cuda.graph(P.graph, stream=st):
             step()
         st.synchronize()
-        P.bytes = (P.ws.numel() + 2 * P.ids.numel() * 4 + P.items.numel() * 4 +
-                   P.off.numel() * 8 + (cap * 64 * 4 if gated else 0))
+        P.bytes = self._plan_bytes(target, k)
         self.plans[key] = P
         return P
 
@@ -268,6 +306,7 @@ class Server:
         self.budget = hbm_budget if hbm_budget is not None else int(self.ex.free_memory() * 0.5)
         self.in_use = 0
         self.waited_for_memory = 0
+        self.released = 0
         self.groups = 0
 
     def run(self, requests: Sequence[Request], clock=time.perf_counter) -> List[Result]:
@@ -278,6 +317,9 @@ class Server:
         n_waiting = 0
         results: List[Result] = []
         busy = [None] * self.n_slots     # (handle, group, bytes) per slot
+        held_bytes = getattr(self.ex, "held_bytes", lambda: 0)
+        new_held = getattr(self.ex, "new_held_bytes", lambda slot, group: 0)
+        release = getattr(self.ex, "release_held", None)
         nxt = 0
         t0 = clock()
         while nxt < len(reqs) or n_waiting or any(b is not None for b in busy):
@@ -296,22 +338,38 @@ class Server:
                                               done))
                     self.in_use -= b[2]
                     busy[i] = None
-            for i in range(self.n_slots):          # admissions
-                if busy[i] is not None or not n_waiting:
-                    continue
+            for _ in range(self.n_slots):          # admissions
+                free = [j for j in range(self.n_slots) if busy[j] is None]
+                if not free or not n_waiting:
+                    break
                 key = min((k for k, d in queues.items() if d), key=lambda k: queues[k][0].arrival)
                 dq = queues[key]
                 group = [dq.popleft() for _ in range(min(self.max_batch, len(dq)))]
+                # a free slot that already holds what this kind of group needs
+                i = min(free, key=lambda j: new_held(j, group))
+                # device memory: what the group uses until it completes, plus
+                # what launching it makes the executor keep for good (graph
+                # plans), against the budget less what is in use or kept
+                avail = self.budget - self.in_use - held_bytes()
                 need = self.ex.need_bytes(group)
-                while need > self.budget - self.in_use and len(group) > 1:
+                hold = new_held(i, group)
+                while need + hold > avail and len(group) > 1:
                     half = len(group) // 2
                     dq.extendleft(reversed(group[half:]))
                     group = group[:half]
                     need = self.ex.need_bytes(group)
-                if need > self.budget - self.in_use:
+                    hold = new_held(i, group)
+                if need + hold > avail:
                     dq.extendleft(reversed(group))
-                    self.waited_for_memory += 1
-                    break                          # wait for a running group to finish
+                    if any(b is not None for b in busy):
+                        self.waited_for_memory += 1
+                        break                      # wait for a running group to finish
+                    if held_bytes() > 0 and release is not None:
+                        release()                  # nothing runs: drop what is kept, retry
+                        self.released += 1
+                        continue
+                    raise MemoryError(f"one request needs {need + hold} bytes of device "
+                                      f"memory; the budget is {self.budget}")
                 n_waiting -= len(group)
                 self.in_use += need
                 self.groups += 1

@@ -94,3 +94,52 @@ def test_groups_keep_arrival_order_within_a_key_under_memory_pressure():
     for target in ("a", "b"):
         order = [r for _, rids, t, _ in ex.launched if t == target for r in rids]
         assert order == sorted(order)
+
+
+class HoldingExecutor(FakeExecutor):
+    """Like a graph executor: the first group of each (slot, index, k) makes a
+    plan of fixed size that stays; groups themselves need nothing more."""
+
+    def __init__(self, plan_bytes):
+        super().__init__(bytes_per_query=0, polls=2)
+        self.plan_bytes = plan_bytes
+        self.plans = set()
+
+    def need_bytes(self, group):
+        return 0
+
+    def new_held_bytes(self, slot, group):
+        return 0 if (slot, group[0].target, group[0].k) in self.plans else self.plan_bytes
+
+    def held_bytes(self):
+        return self.plan_bytes * len(self.plans)
+
+    def release_held(self):
+        assert self.live == 0
+        self.plans.clear()
+
+    def launch(self, slot, group):
+        self.plans.add((slot, group[0].target, group[0].k))
+        assert self.held_bytes() <= self.budget
+        return super().launch(slot, group)
+
+
+def test_memory_held_between_groups_counts_against_the_budget():
+    # room for three plans: the kinds that would need a fourth plan run on
+    # slots that already hold theirs, and every request is still answered
+    ex = HoldingExecutor(plan_bytes=100)
+    ex.budget = 350
+    srv = serving.Server(slots=4, max_batch=4, hbm_budget=350, executor=ex)
+    res = srv.run(_reqs(60, np.random.default_rng(3)))
+    assert sorted(r.rid for r in res) == list(range(60))
+    assert len(ex.plans) <= 3
+    assert srv.released > 0
+    assert srv.in_use == 0
+
+
+def test_request_that_can_never_fit_raises():
+    import pytest
+    ex = FakeExecutor(bytes_per_query=1000)
+    srv = serving.Server(slots=2, max_batch=4, hbm_budget=500, executor=ex)
+    with pytest.raises(MemoryError):
+        srv.run(_reqs(3, np.random.default_rng(4)))
