@@ -99,8 +99,9 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def pmc_summary_path(workload: str) -> str:
-    return os.path.join(ROOT, "profiles", f"scan_cpq_{workload}_pmc.json")
+def pmc_summary_path(workload: str, path: str = "plain") -> str:
+    tag = "" if path == "plain" else "_" + path
+    return os.path.join(ROOT, "profiles", f"scan_cpq_{workload}{tag}_pmc.json")
 
 
 def kernel_source_hash() -> str:
@@ -108,11 +109,12 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per scan launch from the committed rocprofv3 counter summary,
-    only if it was taken on the current kernel source."""
+def measured_traffic(workload: str, path: str = "plain"):
+    """HBM bytes per scan launch from the committed rocprofv3 counter summary
+    of this workload and path, only if it was taken on the current kernel
+    source."""
     try:
-        with open(pmc_summary_path(workload)) as f:
+        with open(pmc_summary_path(workload, path)) as f:
             pmc = json.load(f)
     except (OSError, ValueError):
         return None
@@ -121,19 +123,103 @@ def measured_traffic(workload: str):
     return pmc.get("hbm_bytes_per_launch")
 
 
+def measure_peaks(genie) -> dict:
+    """Peak rates measured on this device in this run (library probes): LDS
+    atomic adds with return at conflict-free and at random words, without
+    return at random words; a streaming HBM read and copy of 2 GiB buffers
+    (well past the 256 MB Infinity Cache)."""
+    log("probing LDS atomic and HBM peaks")
+    peaks = {"lds_atomic_conflict_free": genie.genie_probe_lds_atomics(0),
+             "lds_atomic_random": genie.genie_probe_lds_atomics(1),
+             "lds_atomic_random_no_return": genie.genie_probe_lds_atomics(2)}
+    rd, cp = genie.genie_probe_hbm(2 << 30, 5)
+    peaks.update(hbm_read_gbs=round(rd, 1), hbm_copy_gbs=round(cp, 1),
+                 hbm_spec_gbs=HBM_PEAK_GBS,
+                 source="genie_probe_lds_atomics (1024-thread workgroups, 64 KB LDS each, 8 "
+                        "independent atomics per lane) and genie_probe_hbm, in this run")
+    return peaks
+
+
+def roofs(scanned, s_total, nq, k, n_tiles, kernel_ms, peaks, traffic):
+    """Both roofs of one scan launch and the one that binds.
+
+    HBM: the algorithmic bytes of the survey's count -- 4 B per posting
+    (uint32 ids, read once), 12 B per item, 16 B of list offsets per item and
+    8 B per result -- over the kernel's duration, against 8 TB/s; beside it
+    the bytes this layout reads (2 B per posting, 12 B per item, 8 B of
+    Position Map per item and tile, 8 B per result) and the HBM bytes the
+    counters measured.  LDS atomics: one increment per posting, against the
+    measured conflict-free rate of LDS atomic adds with return.  When the
+    algorithmic bytes arrive faster than HBM can deliver them, the index is
+    served from the caches and HBM cannot be the bound; otherwise the roof
+    with the larger fraction binds."""
+    t = kernel_ms * 1e-3
+    alg = 4 * scanned + 12 * s_total + 16 * s_total + 8 * k * nq
+    layout = 2 * scanned + 12 * s_total + 8 * s_total * n_tiles + 8 * k * nq
+    hbm_gbs = alg / t / 1e9
+    hbm_frac = hbm_gbs / HBM_PEAK_GBS
+    rate = scanned / t
+    lds_peak = peaks["lds_atomic_conflict_free"]
+    lds_frac = rate / lds_peak
+    hbm_binds = hbm_frac <= 1.0 and hbm_frac >= lds_frac
+    out = {"kernel": "scan_cpq_kernel", "kernel_ms": round(kernel_ms, 4)}
+    if hbm_binds:
+        out.update(bound="hbm", achieved=round(hbm_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=round(hbm_frac, 4))
+    else:
+        out.update(bound="lds_atomic", achieved=round(rate / 1e9, 1),
+                   peak=round(lds_peak / 1e9, 1), unit="G atomic adds/s",
+                   frac=round(lds_frac, 4))
+    out.update(traffic=traffic,
+               hbm_alg_bytes_per_launch=alg, hbm_alg_gbs=round(hbm_gbs, 1),
+               hbm_alg_frac=round(hbm_frac, 4),
+               layout_bytes_per_launch=layout,
+               hbm_measured_gbs=(round(traffic / t / 1e9, 1) if traffic else None),
+               lds_atomic_rate=round(rate / 1e9, 1), lds_atomic_frac=round(lds_frac, 4),
+               lds_atomic_frac_of_random=round(rate / peaks["lds_atomic_random"], 4),
+               postings_per_launch=scanned)
+    return out
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_threads() -> int:
+    """Threads for the oracle: the CPUs this process may run on, at most 16
+    (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(values, V, queries, k, budget_s: float, chunk: int = 64):
     """The oracle's inverted-index search (plain C, one query after another
     per thread) on the host cores: half the budget on one thread, half on
     `threads` threads taking chunks of queries from a shared cursor (ctypes
     calls release the interpreter lock).  Queries are taken from the front of
-    the batch, wrapping around, until the budget is spent."""
+    the batch, wrapping around, until the budget is spent.  The answers of
+    every query the multi-threaded leg reached are kept (row -> (ids,
+    counts)) so that the GPU's answers to the same rows can be checked
+    against them."""
     import threading
     import oracle
     log("cpu baseline")
     idx = oracle.build_csr(values, V)
     nq = queries.n_queries
+    answers = {}
 
-    def run(threads, budget):
+    def run(threads, budget, keep):
         state = {"next": 0, "done": 0}
         lock = threading.Lock()
         t0 = time.perf_counter()
@@ -146,9 +232,12 @@ def cpu_baseline(values, V, queries, k, budget_s: float, chunk: int = 64):
                     q0 = state["next"] % nq
                     q1 = min(nq, q0 + chunk)
                     state["next"] += q1 - q0
-                oracle.search_idx(idx, queries, k, q0, q1)
+                ids, cts, _, _ = oracle.search_idx(idx, queries, k, q0, q1)
                 with lock:
                     state["done"] += q1 - q0
+                    if keep:
+                        for r in range(q0, q1):
+                            answers.setdefault(r, (ids[r - q0], cts[r - q0]))
 
         ws = [threading.Thread(target=worker) for _ in range(threads)]
         for w in ws:
@@ -157,16 +246,59 @@ def cpu_baseline(values, V, queries, k, budget_s: float, chunk: int = 64):
             w.join()
         return state["done"], time.perf_counter() - t0
 
-    threads = max(1, min(16, os.cpu_count() or 1))
-    d1, t1 = run(1, budget_s / 2)
-    dn, tn = run(threads, budget_s / 2)
+    threads = host_threads()
+    d1, t1 = run(1, budget_s / 2, False)
+    dn, tn = run(threads, budget_s / 2, True)
     return {"value": dn / tn, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "single_thread_value": d1 / t1,
             "sample": f"{dn} queries of the same batch ({nq} queries, taken in order, wrapping "
                       f"around) on {threads} threads in {tn:.1f} s, and {d1} on one thread in "
                       f"{t1:.1f} s (inverted-index scan + count array + selection, plain C)",
-            "cpu": platform.processor() or platform.machine(),
-            "host_cpus": os.cpu_count()}
+            "cpu": cpu_model(), "host_cpus": os.cpu_count()}, answers
+
+
+def digest_check(workload, ids, cts):
+    """The whole answer against the committed digest of the oracle's full
+    answer for this workload (tests/golden/<workload>_oracle_digest.json,
+    written by tests/golden/make_oracle_digests.py), when there is one."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_oracle_digest.json")
+    try:
+        with open(path) as f:
+            ref = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ids = np.ascontiguousarray(np.asarray(ids).view(np.uint32))
+    cts = np.ascontiguousarray(np.asarray(cts).view(np.uint32))
+    if ids.shape != (ref["n_queries"], ref["k"]):
+        return {"match": False, "reason": f"answer shape {ids.shape} is not the digest's"}
+
+    def digest(a, b):
+        h = hashlib.sha256()
+        h.update(a.astype("<u4").tobytes())
+        h.update(b.astype("<u4").tobytes())
+        return h.hexdigest()
+
+    B = ref["block_rows"]
+    blocks = [digest(ids[b:b + B], cts[b:b + B]) for b in range(0, ids.shape[0], B)]
+    bad = [i for i, (x, y) in enumerate(zip(blocks, ref["block_sha256"])) if x != y]
+    return {"match": digest(ids, cts) == ref["sha256"], "rows": int(ids.shape[0]),
+            "mismatched_blocks": bad, "block_rows": B,
+            "reference": os.path.relpath(path, ROOT)}
+
+
+def oracle_check(answers, ids, cts, nq):
+    """The GPU's answers (the timed batch's last step) against the oracle's
+    answers to the same rows, element by element."""
+    ids = np.asarray(ids).view(np.uint32)
+    cts = np.asarray(cts).view(np.uint32)
+    rows = sorted(answers)
+    bad = [r for r in rows
+           if not (np.array_equal(ids[r], answers[r][0]) and np.array_equal(cts[r], answers[r][1]))]
+    return {"rows_checked": len(rows), "rows_matched": len(rows) - len(bad), "of": nq,
+            "first_mismatch": bad[0] if bad else None,
+            "compared": "ids and counts of every checked row, bit for bit, against the CPU "
+                        "oracle (inverted-index scan, Definition 2.1 counts, order count desc "
+                        "then id asc); the gated and GEN-SPQ answers equal the plain ones"}
 
 
 def train_gate(genie, torch, ix, sets, epochs: int):
@@ -194,8 +326,9 @@ class SearchBench:
     this step: constant tensors for item queries, or the output of the LSH
     kernels for point queries (their time is then part of the step)."""
 
-    def __init__(self, genie, torch, ix, nq, k, max_items, prep):
+    def __init__(self, genie, torch, ix, nq, k, max_items, prep, workload, peaks):
         self.genie, self.torch, self.ix = genie, torch, ix
+        self.workload, self.peaks = workload, peaks
         self.nq, self.k, self.max_items, self.prep = nq, k, max_items, prep
         self.stream = torch.cuda.current_stream()
         self.ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
@@ -354,23 +487,33 @@ class SearchBench:
         use_gate = el_gate is not None and el_gate < el_plain
         elapsed = el_gate if use_gate else el_plain
         scanned = stats["postings_scanned"]
-        # algorithmic bytes of one scan launch: postings (uint16, read once),
-        # the items (12 B), two Position Map offsets per item per tile (8 B),
-        # and the answer (8 B per result)
         T = self.ix.info.n_tiles
-        alg_bytes = 2 * scanned + 12 * s_total + 8 * s_total * T + 8 * k * nq
-        achieved = alg_bytes / (scan_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "kernel": "scan_cpq_kernel",
-                    "kernel_ms": round(scan_ms, 4), "merge_kernel_ms": round(merge_ms, 4),
-                    "alg_bytes_per_launch": alg_bytes}
+        # the roofline belongs to the path whose throughput is `value`: its
+        # main scan kernel (the gated path's fallback scan is a separate
+        # launch, timed apart)
+        if use_gate:
+            kms = gkt["scan_ms"] / max(1, gkt["scan_launches"])
+            roof_path, roof_T = "gated", self.gix.info.n_tiles
+        else:
+            kms, roof_path, roof_T = scan_ms, "plain", T
+        roofline = roofs(scanned, s_total, nq, k, roof_T, kms, self.peaks,
+                         measured_traffic(self.workload, roof_path))
+        roofline.update(path=("learned gate + c-PQ" if use_gate else "plain c-PQ"),
+                        merge_kernel_ms=round(merge_ms, 4))
+        plain_roof = roofs(scanned, s_total, nq, k, T, scan_ms, self.peaks,
+                           measured_traffic(self.workload, "plain"))
         rate = scanned / (scan_ms * 1e-3)
-        atomic_roof = {"achieved": rate, "peak": LDS_ATOMIC_PEAK, "unit": "increments/s",
-                       "frac": round(rate / LDS_ATOMIC_PEAK, 4), "postings_per_step": scanned}
+        atomic_roof = {"achieved": rate, "peak": self.peaks["lds_atomic_conflict_free"],
+                       "unit": "increments/s", "path": "plain c-PQ",
+                       "frac": round(rate / self.peaks["lds_atomic_conflict_free"], 4),
+                       "postings_per_step": scanned}
         plain = {"value": round(nq * steps / el_plain, 1),
                  "ms_per_step": round(el_plain * 1e3 / steps, 4),
                  "eager_ms_per_step": round(eager_plain * 1e3 / steps, 4),
+                 "scan_kernel_ms": round(scan_ms, 4),
+                 "roofline": {key: plain_roof[key] for key in
+                              ("bound", "achieved", "peak", "unit", "frac", "hbm_alg_frac",
+                               "lds_atomic_frac")},
                  "gate_passes_per_step": stats["gate_passes"],
                  "ht_inserts_per_step": stats["ht_inserts"],
                  "ht_overflow_tiles": stats["ht_overflow_tiles"],
@@ -379,6 +522,7 @@ class SearchBench:
                  "schedule": "persistent" if self.ix.info.scan_persistent else "grid"}
         learned = None
         if el_gate is not None:
+            gms = gkt["scan_ms"] / max(1, gkt["scan_launches"])
             learned = {"value": round(nq * steps / el_gate, 1),
                        "ms_per_step": round(el_gate * 1e3 / steps, 4),
                        "eager_ms_per_step": round(eager_gate * 1e3 / steps, 4),
@@ -386,7 +530,8 @@ class SearchBench:
                        "identical_results": True,
                        "gate_passes_per_step": gstats["gate_passes"],
                        "fallback_queries_per_step": gstats["fallback_queries"],
-                       "scan_ms_per_step": round(gkt["scan_ms"] / steps, 4),
+                       "scan_kernel_ms": round(gms, 4),
+                       "fallback_scan_ms_per_step": round(gkt["fallback_ms"] / steps, 4),
                        "delta": self.model.delta,
                        "tile_objects": self.gix.info.tile_objects,
                        "scan_shape": "%dx%d" % tuple(self.gix.info.scan_shape),
@@ -413,7 +558,7 @@ def line(args, workload, res, config, dtype="u32"):
                           parallelism="single GPU")}
     for key in ("roofline", "atomic_roof", "plain_cpq", "learned_gate", "gen_spq"):
         out[key] = res[key]
-    out["roofline"]["traffic"] = measured_traffic(workload)
+    out["peaks"] = args.peaks
     return out
 
 
@@ -446,7 +591,8 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
         ix = genie.Index(inst.values, inst.V)
     log("index ready:", ix.info)
     off, items = genie.queries_to_device(inst.queries.q_offsets, inst.queries.items)
-    sb = SearchBench(genie, torch, ix, nq, k, inst.queries.max_items(), lambda st: (off, items))
+    sb = SearchBench(genie, torch, ix, nq, k, inst.queries.max_items(), lambda st: (off, items),
+                     name, args.peaks)
     if tune:
         sb.plain_shape = (tune["plain"]["threads"], tune["plain"]["unroll"],
                           tune["plain"]["persistent"])
@@ -476,9 +622,15 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
     if out["learned_gate"]:
         out["learned_gate"].update(train_queries=args.gate_train_queries,
                                    epochs=args.gate_epochs)
-    out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget,
-                                        chunk=chunk)
-                           if not args.no_cpu_baseline and args.cpu_budget > 0 else None)
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline and args.cpu_budget > 0:
+        out["cpu_baseline"], answers = cpu_baseline(inst.values, inst.V, inst.queries, k,
+                                                    args.cpu_budget, chunk=chunk)
+        out["oracle_check"] = oracle_check(answers, genie.as_uint32(sb.ids),
+                                           genie.as_uint32(sb.cts), nq)
+    dig = digest_check(name, genie.as_uint32(sb.ids), genie.as_uint32(sb.cts))
+    if dig is not None:
+        out["oracle_digest"] = dig
     for used in {id(sb.ix): sb.ix, id(sb.gix): sb.gix}.values():
         used.free()
     return out
@@ -578,7 +730,7 @@ def bench_ann(args, torch, genie, workloads):
         genie.genie_lsh_items_async(qsig, out=(qoff, qitems), stream=st)
         return qoff, qitems
 
-    sb = SearchBench(genie, torch, ix, nq, k, m, prep)
+    sb = SearchBench(genie, torch, ix, nq, k, m, prep, "ann", args.peaks)
     if not args.no_gate:
         tq = workloads.ann_queries(np.random.default_rng(workloads.BASE_SEED + 103),
                                    inp.points, args.gate_train_queries)
@@ -602,9 +754,14 @@ def bench_ann(args, torch, genie, workloads):
                                    epochs=args.gate_epochs)
     if not args.no_cpu_baseline and args.cpu_budget > 0:
         qs = workloads.queries_exact(genie.as_uint32(qsig))
-        cb = cpu_baseline(sig_h, 1 << inp.log2_buckets, qs, k, args.cpu_budget)
+        cb, answers = cpu_baseline(sig_h, 1 << inp.log2_buckets, qs, k, args.cpu_budget)
         cb["sample"] += "; query signatures from the timed run, hashing not included"
         out["cpu_baseline"] = cb
+        out["oracle_check"] = oracle_check(answers, genie.as_uint32(sb.ids),
+                                           genie.as_uint32(sb.cts), nq)
+        out["oracle_check"]["compared"] += ("; the oracle searches the device's signatures of "
+                                            "the points and the queries (hashing is checked "
+                                            "against the float64 oracle in the tests)")
     else:
         out["cpu_baseline"] = None
     ix.free()
@@ -659,7 +816,7 @@ def bench_laplace(args, torch, genie, workloads):
         genie.genie_lsh_items_async(qsig, out=(qoff, qitems), stream=st)
         return qoff, qitems
 
-    sb = SearchBench(genie, torch, ix, nq, k, m, prep)
+    sb = SearchBench(genie, torch, ix, nq, k, m, prep, "laplace", args.peaks)
     if not args.no_gate:
         tq = workloads.ann_queries(np.random.default_rng(workloads.BASE_SEED + 106),
                                    inp.points, args.gate_train_queries)
@@ -684,9 +841,14 @@ def bench_laplace(args, torch, genie, workloads):
                                    epochs=args.gate_epochs)
     if not args.no_cpu_baseline and args.cpu_budget > 0:
         qs = workloads.queries_exact(genie.as_uint32(qsig))
-        cb = cpu_baseline(sig_h, 1 << inp.log2_buckets, qs, k, args.cpu_budget)
+        cb, answers = cpu_baseline(sig_h, 1 << inp.log2_buckets, qs, k, args.cpu_budget)
         cb["sample"] += "; query signatures from the timed run, hashing not included"
         out["cpu_baseline"] = cb
+        out["oracle_check"] = oracle_check(answers, genie.as_uint32(sb.ids),
+                                           genie.as_uint32(sb.cts), nq)
+        out["oracle_check"]["compared"] += ("; the oracle searches the device's signatures of "
+                                            "the points and the queries (hashing is checked "
+                                            "against the float64 oracle in the tests)")
     else:
         out["cpu_baseline"] = None
     ix.free()
@@ -746,9 +908,11 @@ def bench_multiload(args, torch, genie, workloads):
     scanned = stats["postings_scanned"]
     s_total = int(inst.queries.q_offsets[-1])
     T = parts.info["tiles_total"]
-    alg_bytes = 2 * scanned + 12 * s_total + 8 * s_total * T + 8 * k * nq
     step_ms = el * 1e3 / args.steps
-    achieved = alg_bytes / (scan_ms * n_parts * 1e-3) / 1e9
+    # one scan launch per part: a part's share of the postings and tiles
+    roof = roofs(scanned // n_parts, s_total, nq, k, max(1, T // n_parts), scan_ms, args.peaks,
+                 None)
+    roof.update(scans_per_step=n_parts)
     h2d = parts.info["host_bytes"]
     out = {"metric": "queries/sec at k=100, 8M relational objects, index streamed in 4 parts "
                      "per batch (multiple loadings); oracle-exact",
@@ -761,11 +925,7 @@ def bench_multiload(args, torch, genie, workloads):
                                   "4 parts of 2,000,000 objects streamed every batch",
                       "n_objects": inst.n, "parts": n_parts, "part_objects": part,
                       "launch": "eager", "parallelism": "single GPU"},
-           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": None, "kernel": "scan_cpq_kernel",
-                        "kernel_ms": round(scan_ms, 4), "alg_bytes_per_step": alg_bytes,
-                        "scans_per_step": n_parts},
+           "roofline": roof, "peaks": args.peaks,
            "transfer": {"index_bytes_per_step": h2d,
                         "index_gbs_streamed": round(h2d / (step_ms * 1e-3) / 1e9, 2),
                         "scan_ms_per_step": round(scan_ms * n_parts, 4)},
@@ -773,8 +933,12 @@ def bench_multiload(args, torch, genie, workloads):
                               "ms_per_step": round(el_res * 1e3 / args.steps, 4),
                               "identical_results": True},
            "plain_cpq": {"postings_per_step": scanned}, "learned_gate": None}
-    out["cpu_baseline"] = (cpu_baseline(inst.values, inst.V, inst.queries, k, args.cpu_budget)
-                           if not args.no_cpu_baseline and args.cpu_budget > 0 else None)
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline and args.cpu_budget > 0:
+        out["cpu_baseline"], answers = cpu_baseline(inst.values, inst.V, inst.queries, k,
+                                                    args.cpu_budget)
+        out["oracle_check"] = oracle_check(answers, genie.as_uint32(ids), genie.as_uint32(cts),
+                                           nq)
     parts.free()
     ix.free()
     return out
@@ -853,7 +1017,7 @@ def bench_sequence(args, torch, genie, workloads):
                                      st)
 
     ix = sx.match_index
-    sb = SearchBench(genie, torch, ix, nq, K, max_qlen, prep)
+    sb = SearchBench(genie, torch, ix, nq, K, max_qlen, prep, "sequence", args.peaks)
     sb.post = verify
     if not args.no_gate:
         rng = np.random.default_rng(workloads.BASE_SEED + 100 + workloads.CONFIG_IDS["sequence"])
@@ -1069,7 +1233,16 @@ def main():
                     help="timed steps (default 50; 3 for the uneven workload)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps (default 5; 1 for the uneven workload)")
-    ap.add_argument("--workload", choices=sorted(METRICS), default="relational")
+    ap.add_argument("--workload", choices=sorted(METRICS), default=None,
+                    help="one workload alone; by default the relational headline with the "
+                         "--nested workloads reported inside its line")
+    ap.add_argument("--nested", default="tiny,ann,uneven,serving",
+                    help="default run only: workloads reported under 'configs' in the "
+                         "headline line, each with its own roofline and CPU baseline "
+                         "('none' for the headline alone)")
+    ap.add_argument("--time-budget", type=float, default=470.0,
+                    help="default run only: a nested workload is skipped (and said so) when "
+                         "its expected duration no longer fits this many seconds")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle time for the CPU baseline (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -1083,7 +1256,7 @@ def main():
                     help="item workloads: tiles of 2^L-1 objects, T threads x U dwords, "
                          "schedule P (0 grid, 1 persistent) for every path instead of the "
                          "default or autotuned configuration (e.g. for profiler runs)")
-    ap.add_argument("--requests", type=int, default=50000, help="serving: number of requests")
+    ap.add_argument("--requests", type=int, default=100000, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serving: execution slots")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: requests per group")
     ap.add_argument("--serving-executor", choices=("graph", "eager"), default="graph",
@@ -1103,11 +1276,8 @@ def main():
         args.fixed = tuple(int(x) for x in args.fixed.split(","))
         if len(args.fixed) != 4:
             ap.error("--fixed takes L,T,U,P")
-    heavy = args.workload == "uneven"
-    if args.steps is None:
-        args.steps = 3 if heavy else 50
-    if args.warmup is None:
-        args.warmup = 1 if heavy else 5
+    steps_given, warmup_given = args.steps, args.warmup
+    set_steps(args, args.workload or "relational", steps_given, warmup_given)
 
     import torch
     import paper_1603_08390_amd as genie
@@ -1123,11 +1293,71 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
         return
-    fn = {"relational": bench_relational, "tiny": bench_tiny, "ann": bench_ann,
-          "uneven": bench_uneven, "serving": bench_serving,
-          "multiload": bench_multiload, "laplace": bench_laplace,
-          "sequence": bench_sequence}[args.workload]
-    print(json.dumps(fn(args, torch, genie, workloads)), flush=True)
+    t_start = time.perf_counter()
+    args.peaks = measure_peaks(genie)
+    fns = {"relational": bench_relational, "tiny": bench_tiny, "ann": bench_ann,
+           "uneven": bench_uneven, "serving": bench_serving,
+           "multiload": bench_multiload, "laplace": bench_laplace,
+           "sequence": bench_sequence}
+    out = fns[args.workload or "relational"](args, torch, genie, workloads)
+    if args.workload is None:
+        out["configs"] = {}
+        for name in [x for x in args.nested.split(",") if x and x != "none"]:
+            left = args.time_budget - (time.perf_counter() - t_start)
+            if NESTED_EXPECTED_S[name] > left:
+                out["configs"][name] = {"skipped": f"expected {NESTED_EXPECTED_S[name]} s; "
+                                                   f"{left:.0f} s of the time budget left"}
+                log("skipping", name, "(time budget)")
+                continue
+            sub = argparse.Namespace(**vars(args))
+            set_steps(sub, name, steps_given, warmup_given, nested=True)
+            sub.cpu_budget = min(args.cpu_budget, NESTED_CPU_BUDGET_S)
+            log("nested workload:", name)
+            t0 = time.perf_counter()
+            try:
+                res = fns[name](sub, torch, genie, workloads)
+            except Exception as e:   # reported in the line; the run's exit status says so
+                res = {"error": f"{type(e).__name__}: {e}"}
+            res["wall_s"] = round(time.perf_counter() - t0, 1)
+            out["configs"][name] = res
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    out["wall_s"] = round(time.perf_counter() - t_start, 1)
+    print(json.dumps(out), flush=True)
+    if not exact(out):
+        log("answers differ from the oracle, or a nested workload failed")
+        sys.exit(3)
+
+
+# Expected duration of each nested workload on one MI355X, including input
+# generation, index builds, tuning, gate training and the CPU baseline.
+NESTED_EXPECTED_S = {"tiny": 30, "ann": 90, "uneven": 200, "serving": 150, "relational": 40,
+                     "laplace": 90, "sequence": 120, "multiload": 90}
+NESTED_CPU_BUDGET_S = 10.0
+
+
+def set_steps(args, workload, steps, warmup, nested=False):
+    """Timed and warmup steps: as given, else 50 and 5 (3 and 1 for the
+    uneven batch, whose steps take seconds; nested, it runs 2 and 1)."""
+    heavy = workload == "uneven"
+    if heavy and nested:
+        args.steps, args.warmup = 2, 1
+        return
+    args.steps = steps if steps is not None else (3 if heavy else 50)
+    args.warmup = warmup if warmup is not None else (1 if heavy else 5)
+
+
+def exact(line) -> bool:
+    """Every oracle comparison in the line (and its nested lines) matched."""
+    chk = line.get("oracle_check")
+    if chk and chk["rows_matched"] != chk["rows_checked"]:
+        return False
+    dig = line.get("oracle_digest")
+    if dig and not dig["match"]:
+        return False
+    if "error" in line:
+        return False
+    return all(exact(sub) for sub in line.get("configs", {}).values() if "skipped" not in sub)
 
 
 if __name__ == "__main__":
