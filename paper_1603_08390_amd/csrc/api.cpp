@@ -108,6 +108,27 @@ extern "C" int genie_build_index(const uint32_t *values, uint64_t n, uint32_t d,
 
 namespace genie {
 
+// Permutes the len ids of one run that starts at element `start` of its
+// tile so that element j holds, where the run allows, an id whose 8-bit
+// counter word (id / 4) falls in LDS bank ((start + j) / 2) mod 64; when the
+// run has no id left for that bank, the next bank that has one is taken.
+static void bank_order(uint16_t *run, uint32_t start, uint32_t len,
+                       std::vector<uint16_t> (&bucket)[64]) {
+    if (len < 4)
+        return;
+    for (auto &v : bucket)
+        v.clear();
+    for (uint32_t j = 0; j < len; j++)
+        bucket[(run[j] >> 2) & 63].push_back(run[j]);
+    for (uint32_t j = 0; j < len; j++) {
+        uint32_t g = ((start + j) >> 1) & 63;
+        while (bucket[g].empty())
+            g = (g + 1) & 63;
+        run[j] = bucket[g].back();
+        bucket[g].pop_back();
+    }
+}
+
 // Shared by both index forms: keys_of(o, emit) calls emit(key) once for
 // every keyword of object o and returns false if a keyword is out of range.
 template <class KeysOf>
@@ -217,6 +238,7 @@ static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nk
     next.store(0);
     auto fill_tiles = [&]() {
         std::vector<uint32_t> fill(nkeys);
+        std::vector<uint16_t> bucket[64];
         for (;;) {
             uint32_t t = next.fetch_add(1);
             if (t >= T)
@@ -227,6 +249,21 @@ static int build_host_index_impl(uint64_t n, uint32_t d, uint32_t V, uint64_t nk
             // objects in ascending id order: every run ascends
             for (uint64_t o = o0; o < o1; o++)
                 keys_of(o, [&](uint64_t key) { dst[fill[key]++] = (uint16_t)(o - o0); });
+            // Bank order: the order inside a run does not change any count, so
+            // each run is permuted such that the id at element j, which the
+            // scan reads in dword (start + j) / 2 by lane (start + j) / 2 mod
+            // 64 of a wave, has its 8-bit counter word in LDS bank
+            // (start + j) / 2 mod 64 when the run holds such an id: the 64
+            // atomics of one wave instruction then tend to hit 64 different
+            // banks.  (8-bit counters are the common width; other widths get
+            // an order as good as any.)
+            for (uint64_t key = 0; key < nkeys; key++) {
+                const uint32_t b = toff[(uint64_t)t * (nkeys + 1) + key];
+                const uint32_t e = toff[(uint64_t)t * (nkeys + 1) + key + 1];
+                const uint32_t pads = tpad[(uint64_t)t * (nkeys + 1) + key + 1] -
+                                      tpad[(uint64_t)t * (nkeys + 1) + key];
+                bank_order(dst + b, b, (e - b) - pads, bucket);
+            }
         }
     };
     {

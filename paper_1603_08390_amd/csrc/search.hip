@@ -545,7 +545,7 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         const uint32_t at_m1 = at_reg - 1;   // val = f + 1 >= AT  <=>  f >= AT - 1
         // all increments first (no branch between the LDS atomics, so their
         // latencies overlap), then the gate check
-        uint32_t f[2 * U];
+        uint32_t f[2 * U], shs[2 * U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
 #pragma unroll
@@ -571,10 +571,19 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                     __hip_atomic_fetch_add(cw, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     f[2 * u + h] = 0;
                 } else {
-                    const uint32_t old = lds_add(cw, inc);
-                    f[2 * u + h] = __builtin_amdgcn_ubfe(old, sh, BITS);
+                    f[2 * u + h] = lds_add(cw, inc);   // the word before the add
+                    shs[2 * u + h] = sh;
                 }
             }
+        }
+        // Every atomic of the step is issued before the first returned word
+        // is used: left to itself the compiler extracts the first fields early
+        // and waits for the first atomics before issuing the later ones.
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!SPQ) {
+#pragma unroll
+            for (int j = 0; j < 2 * U; j++)
+                f[j] = __builtin_amdgcn_ubfe(f[j], shs[j], BITS);
         }
         // Algorithm 1's gate check, first for the whole wave at once: the
         // largest previous count of the lane's postings against AT - 1
