@@ -301,10 +301,15 @@ def oracle_check(answers, ids, cts, nq):
                         "then id asc); the gated and GEN-SPQ answers equal the plain ones"}
 
 
-def train_gate(genie, torch, ix, sets, epochs: int):
+def train_gate(genie, torch, ix, sets, epochs: int, args=None):
     """Gate model trained on (features, k-th count of the plain method) pairs
-    of the given (d_q_offsets, d_items, max_items, k) query sets."""
+    of the given (d_q_offsets, d_items, max_items, k) query sets; with
+    --load-gate it is read from a file a run with --save-gate wrote (so that
+    a profiler run holds no training launches)."""
     from paper_1603_08390_amd import gate as gate_mod
+    if args is not None and getattr(args, "load_gate", None):
+        log("gate model from", args.load_gate)
+        return gate_mod.GateModel.load(args.load_gate)
     xs, ys = [], []
     for (toff, titems, tmax, k) in sets:
         _, t_cts, _ = genie.genie_search_async(ix, toff, titems, k, tmax)
@@ -316,6 +321,8 @@ def train_gate(genie, torch, ix, sets, epochs: int):
     log("training the gate on", tx.shape[0], "queries")
     model.train(tx, ty, epochs=epochs, batch=256, lr=2e-3, tau=0.1)
     model.calibrate(model.predict(tx).cpu().numpy(), ty.cpu().numpy(), target=0.01)
+    if args is not None and getattr(args, "save_gate", None):
+        model.save(args.save_gate)
     return model
 
 
@@ -402,6 +409,28 @@ class SearchBench:
             step()
         torch.cuda.synchronize()
         return time.perf_counter() - t0
+
+    def profile(self, path, steps, warmup):
+        """Only one path's eager steps (profiler runs): the scan kernel's
+        HIP-event mean duration, to set beside the profiler's."""
+        g, torch = self.genie, self.torch
+        step = self.plain_step if path == "plain" else self.gated_step
+        ix = self.ix if path == "plain" else self.gix
+        g.genie_kernel_timing_enable(True)
+        g.genie_kernel_timing_read(reset=True)
+        el = self.timed(step, steps, warmup)
+        kt = g.genie_kernel_timing_read(reset=True)
+        g.genie_kernel_timing_enable(False)
+        st = g.workspace_stats(self.ws if path == "plain" else self.gws)
+        return {"profile_path": path, "steps": steps, "warmup": warmup,
+                "ms_per_step": round(el * 1e3 / steps, 4),
+                "scan_kernel_ms": round(kt["scan_ms"] / max(1, kt["scan_launches"]), 4),
+                "scan_launches": kt["scan_launches"],
+                "merge_kernel_ms": round(kt["merge_ms"] / max(1, kt["merge_launches"]), 4),
+                "postings_per_step": st["postings_scanned"] if path == "plain" else None,
+                "stats": st, "tile_objects": ix.info.tile_objects,
+                "scan_shape": "%dx%d" % tuple(ix.info.scan_shape),
+                "schedule": schedule_name(ix, self.nq)}
 
     def run(self, steps, warmup, s_total, graph=False):
         """Each path: K eager steps with the library's kernel event pairs
@@ -519,7 +548,7 @@ class SearchBench:
                  "ht_overflow_tiles": stats["ht_overflow_tiles"],
                  "tile_objects": self.ix.info.tile_objects,
                  "scan_shape": "%dx%d" % tuple(self.ix.info.scan_shape),
-                 "schedule": "persistent" if self.ix.info.scan_persistent else "grid"}
+                 "schedule": schedule_name(self.ix, self.nq)}
         learned = None
         if el_gate is not None:
             gms = gkt["scan_ms"] / max(1, gkt["scan_launches"])
@@ -535,13 +564,22 @@ class SearchBench:
                        "delta": self.model.delta,
                        "tile_objects": self.gix.info.tile_objects,
                        "scan_shape": "%dx%d" % tuple(self.gix.info.scan_shape),
-                       "schedule": "persistent" if self.gix.info.scan_persistent else "grid"}
+                       "schedule": schedule_name(self.gix, self.nq)}
         return {"value": round(nq * steps / elapsed, 1),
                 "ms_per_step": round(elapsed * 1e3 / steps, 4), "gen_spq": spq,
                 "path": "learned gate + c-PQ (exact fallback)" if use_gate else "plain c-PQ",
                 "launch": "HIP graph replay" if graph else "eager",
                 "roofline": roofline, "atomic_roof": atomic_roof,
                 "plain_cpq": plain, "learned_gate": learned}
+
+
+def schedule_name(ix, nq):
+    """The scan schedule a search of nq queries runs with on this index
+    (schedule 2 is persistent from 1,024 (query, tile) pairs on)."""
+    sched = ix.info.scan_persistent
+    if sched == 2:
+        sched = 1 if nq * ix.info.n_tiles >= 1024 else 0
+    return "persistent" if sched == 1 else "grid"
 
 
 def use_graph(args, workload):
@@ -600,7 +638,7 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
         tq = train_queries(np.random.default_rng(workloads.BASE_SEED + 100 + workloads.CONFIG_IDS[name]))
         toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
         sb.model = train_gate(genie, torch, ix, [(toff, titems, tq.max_items(), k)],
-                              args.gate_epochs)
+                              args.gate_epochs, args)
         if tune:
             pred = sb.model.predict(genie.genie_gate_features_async(ix, soff, sitems, k))
             tune["gated"] = tune_tilings(indexes, soff, sitems, k, sq.max_items(), reps=2,
@@ -611,6 +649,8 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
     for lg, other in indexes.items():
         if other is not sb.ix and other is not sb.gix:
             other.free()
+    if args.profile_path:
+        return sb.profile(args.profile_path, args.steps, args.warmup)
     res = sb.run(args.steps, args.warmup, int(inst.queries.q_offsets[-1]),
                  graph=use_graph(args, name))
     cfg = {"workload": describe, "n_objects": inst.n, "n_dims": inst.d, "n_buckets": inst.V,
@@ -737,7 +777,9 @@ def bench_ann(args, torch, genie, workloads):
         tsig = genie.genie_lsh_signatures(torch.from_numpy(tq).cuda(), lsh["a"], lsh["b"],
                                           lsh["w"], lsh["rehash"], lsh["log2_buckets"])
         toff, titems = genie.genie_lsh_items_async(tsig)
-        sb.model = train_gate(genie, torch, ix, [(toff, titems, m, k)], args.gate_epochs)
+        sb.model = train_gate(genie, torch, ix, [(toff, titems, m, k)], args.gate_epochs, args)
+    if args.profile_path:
+        return sb.profile(args.profile_path, args.steps, args.warmup)
     res = sb.run(args.steps, args.warmup, nq * m, graph=use_graph(args, "ann"))
     P = torch.from_numpy(inp.points).cuda()
     rec, ratio = ann_quality(torch, P, qpts, sb.ids, k)
@@ -823,7 +865,9 @@ def bench_laplace(args, torch, genie, workloads):
         tsig = genie.genie_rbh_signatures(torch.from_numpy(tq).cuda(), g, u, seeds,
                                           inp.log2_buckets)
         toff, titems = genie.genie_lsh_items_async(tsig)
-        sb.model = train_gate(genie, torch, ix, [(toff, titems, m, k)], args.gate_epochs)
+        sb.model = train_gate(genie, torch, ix, [(toff, titems, m, k)], args.gate_epochs, args)
+    if args.profile_path:
+        return sb.profile(args.profile_path, args.steps, args.warmup)
     res = sb.run(args.steps, args.warmup, nq * m, graph=use_graph(args, "laplace"))
     P = torch.from_numpy(inp.points).cuda()
     rec, ratio = laplace_quality(torch, P, qpts, sb.ids, k)
@@ -1101,6 +1145,7 @@ def bench_serving(args, torch, genie, workloads):
                     q = int(rng.integers(0, inp.queries.shape[0]))
                     g.append(serving.Request(i, "ann", kk_, 0.0, point=inp.queries[q]))
             row = {"target": target, "k": kk_, "requests": len(g)}
+            log("serving group alone:", target, "k =", kk_)
             for use_gate in ((False, True) if not args.no_gate else (False,)):
                 ex = serving.GpuExecutor(res, 1, use_gate)
                 for _ in range(2):
@@ -1156,6 +1201,8 @@ def bench_serving(args, torch, genie, workloads):
         finally:
             gc.enable()
         wall = max(r.done for r in done)   # the loop's own clock: start -> last completion
+        log("serving run:", "gate" if use_gate else "plain", "graphs" if graphs else "eager",
+            len(batch), "requests,", srv.groups, "groups,", round(wall, 2), "s")
         s = serving.latency_summary(done, wall)
         s.update(groups=srv.groups, waited_for_memory=srv.waited_for_memory)
         return {r.rid: r for r in done}, {key: (round(v, 3) if isinstance(v, float) else v)
@@ -1263,6 +1310,13 @@ def main():
                     help="serving: replay per-(slot, index, k) HIP graphs, or launch eagerly")
     ap.add_argument("--loads", default="0.3,0.5,0.7,0.9",
                     help="serving: offered loads as fractions of the saturated plain rate")
+    ap.add_argument("--profile-path", choices=("plain", "gated"), default=None,
+                    help="profiler runs (item and ANN workloads): only this path's eager "
+                         "steps; no graph, ablation, CPU baseline or nested workloads")
+    ap.add_argument("--save-gate", default=None, metavar="PATH",
+                    help="write the trained gate model here")
+    ap.add_argument("--load-gate", default=None, metavar="PATH",
+                    help="read the gate model from here instead of training it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 3 times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -1294,6 +1348,14 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
         return
     t_start = time.perf_counter()
+    if args.profile_path:
+        args.nested = "none"
+        args.peaks = None
+        out = {"relational": bench_relational, "tiny": bench_tiny, "ann": bench_ann,
+               "uneven": bench_uneven, "laplace": bench_laplace}[args.workload or "relational"](
+                   args, torch, genie, workloads)
+        print(json.dumps(out), flush=True)
+        return
     args.peaks = measure_peaks(genie)
     fns = {"relational": bench_relational, "tiny": bench_tiny, "ann": bench_ann,
            "uneven": bench_uneven, "serving": bench_serving,

@@ -82,7 +82,7 @@ typedef struct {
     uint64_t device_bytes;     /* device memory held by the index */
     uint32_t scan_threads;     /* scan kernel launch shape in use (see */
     uint32_t scan_unroll;      /* genie_index_set_scan_shape) */
-    uint32_t scan_persistent;  /* schedule (genie_index_set_scan_schedule) */
+    uint32_t scan_persistent;  /* schedule 0, 1 or 2 (genie_index_set_scan_schedule) */
 } genie_index_info;
 
 /*
@@ -132,15 +132,22 @@ void genie_free_index(genie_index *ix);
 int genie_index_set_scan_shape(genie_index *ix, uint32_t threads, uint32_t unroll);
 
 /*
- * Schedule of the scan kernel for searches on this index.  0 (the
- * default): one workgroup per (query, tile) pair, the hardware dispatcher
- * hands pairs to compute units as workgroups finish.  1: persistent
+ * Schedule of the scan kernel for searches on this index.  0: one
+ * workgroup per (query, tile) pair, the hardware dispatcher hands pairs to
+ * compute units as workgroups finish.  1: persistent
  * workgroups, as many as fit the device at once, each taking pairs from its
  * XCD's slice of the pair list through a device counter and then helping
  * the other slices (Section 3.2.1's load balancing: work goes to whichever
- * workgroup is free).  Results do not depend on it; speed may (the
- * autotuner picks it).  Not to be changed while a search on the index is
- * being enqueued.  Errors: GENIE_EINVAL.
+ * workgroup is free); a workgroup claims its next pair and looks up that
+ * pair's runs while it still counts the current one.  2 (the default):
+ * schedule 1 for calls of at least 1,024 (query, tile) pairs, schedule 0
+ * below (a workgroup would count one pair and gain nothing from preparing
+ * the next).  Where the second run table of schedule 1 does not fit in LDS,
+ * and for genie_search_rows_async (whose rows past the live count would all
+ * be claimed), a search runs with schedule 0.
+ * Results do not depend on it; speed may (the autotuner picks it).  Not to
+ * be changed while a search on the index is being enqueued.
+ * Errors: GENIE_EINVAL.
  */
 int genie_index_set_scan_schedule(genie_index *ix, uint32_t persistent);
 
@@ -624,7 +631,9 @@ int genie_kernel_timing_read(genie_kernel_times *out, int reset);
  * issuing steps x 8 32-bit LDS atomic adds, 8 independent ones at a time.
  *   mode 0: with return, lane-consecutive words (no bank conflicts);
  *   mode 1: with return, pseudo-random words of the 64 KB;
- *   mode 2: without return, pseudo-random words.
+ *   mode 2: without return, pseudo-random words;
+ *   mode 3: with return, lane l at word l of a pseudo-random 64-word row
+ *           (one bank per lane, rows scattered).
  *   d_sink: device, n_blocks * 1024 uint32 (written; keeps results live).
  *   *out_per_s: atomic adds per second over the chip (one untimed launch,
  *   then one timed by HIP events).

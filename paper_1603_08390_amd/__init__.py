@@ -232,7 +232,7 @@ class IndexInfo:
     n_postings: int
     device_bytes: int
     scan_shape: tuple      # (threads per workgroup, posting dwords per thread and step)
-    scan_persistent: int   # 0: one workgroup per (query, tile) pair; 1: persistent
+    scan_persistent: int   # 0: one workgroup per (query, tile) pair; 1: persistent; 2: auto
 
 
 class Index:

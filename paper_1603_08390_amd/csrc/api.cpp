@@ -52,7 +52,7 @@ WorkspaceLayout workspace_layout_tiles(uint64_t n_tiles, uint32_t n_queries, uin
 }
 
 int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2,
-                 SearchShape *out, uint32_t ht_log2_cap) {
+                 SearchShape *out, uint32_t ht_log2_cap, bool two_tables) {
     // Counter width b: counts reach at most max_items; one more code (all
     // ones) marks an object already emitted during selection.
     static const int widths[] = {4, 8, 16};
@@ -77,8 +77,9 @@ int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2
     // static part: the Bitmap Counter (a counter for every local id and the
     // padding id) and one word of the persistent schedule
     const size_t bc_words = (size_t(1) << tile_log2) / cpw + 1;
-    // dynamic part: misc, HT, ZA, run table, gate queues
-    size_t words = 32 + (1u << lg) + (max_items + 2) + 2ull * max_items + 1 +
+    // dynamic part: misc, HT, ZA, run table (two for the persistent
+    // schedule, which prepares the next pair's while counting), gate queues
+    size_t words = 32 + (1u << lg) + (max_items + 2) + (two_tables ? 2 : 1) * (2ull * max_items + 1) +
                    (size_t)(threads / 64) * kGateQueue;
     out->bits = bits;
     out->ht_log2 = lg;
@@ -470,8 +471,9 @@ extern "C" int genie_index_set_scan_shape(genie_index *ix, uint32_t threads, uin
 
 extern "C" int genie_index_set_scan_schedule(genie_index *ix, uint32_t persistent) {
     clear_error();
-    if (!ix || persistent > 1) {
-        set_error("scan schedule must be 0 (one workgroup per pair) or 1 (persistent)");
+    if (!ix || persistent > 2) {
+        set_error("scan schedule must be 0 (one workgroup per pair), 1 (persistent) or 2 "
+                  "(persistent for calls of at least 1,024 pairs)");
         return GENIE_EINVAL;
     }
     ix->scan_persistent = (int)persistent;

@@ -53,7 +53,8 @@ struct genie_index {
     int device = 0;
     int scan_threads = kScanThreadsDefault;   // launch shape of the scan kernel
     int scan_unroll = kScanUnrollDefault;
-    int scan_persistent = 0;                  // 1: persistent workgroups over a pair queue
+    int scan_persistent = 2;                  // 0: a workgroup per pair; 1: persistent
+                                              // workgroups; 2: persistent for large calls
     uint32_t ht_log2_cap = 0;                 // Hash Table slots capped at 2^cap (0: no cap)
     bool key_sets = false;                    // built from keyword sets: d = 1, V = keywords
 };
@@ -114,7 +115,7 @@ struct SearchShape {
     size_t lds_bytes = 0;  // dynamic LDS of the scan kernel (the counters are static)
 };
 int search_shape(uint32_t max_items, uint32_t k, int threads, uint32_t tile_log2,
-                 SearchShape *out, uint32_t ht_log2_cap = 0);
+                 SearchShape *out, uint32_t ht_log2_cap = 0, bool two_tables = false);
 
 int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const genie_item *d_items,
                   uint64_t n_items, uint32_t n_queries, uint32_t max_items, uint32_t k, uint32_t *d_out_ids,

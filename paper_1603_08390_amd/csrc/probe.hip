@@ -7,7 +7,9 @@
 //    lane issuing 32-bit LDS atomic adds in groups of 8 independent ones, as
 //    the scan's counting loop does.  Modes: returning adds at lane-consecutive
 //    words (conflict-free), returning adds at pseudo-random words of the 64 KB,
-//    and non-returning adds at pseudo-random words.
+//    non-returning adds at pseudo-random words, and returning adds where
+//    lane l hits word l of a pseudo-random 64-word row (every lane in its
+//    own bank, the rows scattered, as in a bank-ordered scan).
 //  * HBM streaming rate: a read of a device buffer (16-byte loads, coalesced,
 //    grid-stride) and a copy into a second buffer.
 #include <hip/hip_runtime.h>
@@ -50,6 +52,9 @@ void lds_atomic_probe_kernel(uint32_t steps, uint32_t *sink) {
         for (int j = 0; j < kProbeBatch; j++) {
             if (MODE == 0)   // wave w, lane l: word 64 w + l of a 1024-word block
                 addr[j] = (tid + (uint32_t)j * kProbeThreads + s * 128u) & (kProbeWords - 1);
+            else if (MODE == 3)   // lane l: word l of a pseudo-random 64-word row
+                addr[j] = ((mix32(seed + (uint32_t)j * 0x9e3779b9u) << 6) | (tid & 63)) &
+                          (kProbeWords - 1);
             else
                 addr[j] = mix32(seed + (uint32_t)j * 0x9e3779b9u) & (kProbeWords - 1);
         }
@@ -111,13 +116,14 @@ using namespace genie;
 extern "C" int genie_probe_lds_atomics(int mode, uint32_t steps, uint32_t n_blocks,
                                        uint32_t *d_sink, double *out_per_s) {
     clear_error();
-    if (!d_sink || !out_per_s || mode < 0 || mode > 2 || steps == 0 || n_blocks == 0) {
+    if (!d_sink || !out_per_s || mode < 0 || mode > 3 || steps == 0 || n_blocks == 0) {
         set_error("bad probe arguments");
         return GENIE_EINVAL;
     }
     const void *kern = mode == 0 ? (const void *)lds_atomic_probe_kernel<0>
                      : mode == 1 ? (const void *)lds_atomic_probe_kernel<1>
-                                 : (const void *)lds_atomic_probe_kernel<2>;
+                     : mode == 2 ? (const void *)lds_atomic_probe_kernel<2>
+                                 : (const void *)lds_atomic_probe_kernel<3>;
     EventPair ev;
     GENIE_HIP(hipEventCreate(&ev.a));
     GENIE_HIP(hipEventCreate(&ev.b));

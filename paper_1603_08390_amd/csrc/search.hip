@@ -130,8 +130,47 @@ __device__ __attribute__((noinline)) uint32_t last_run_at_or_before(lds_u32 *sp_
 // misc words at the start of the LDS block
 enum : int {
     M_AT = 0, M_NABOVE = 1, M_OVERFLOW = 2, M_INSERTS = 3, M_SCANNED = 4, M_PASSES = 5,
-    M_WAVESUM = 8
+    M_PREFETCH = 6, M_WAVESUM = 8,
+    // cleared for every pair: words below M_KEEP; the persistent schedule keeps
+    // its state above: two run-table slot headers and its claim cursor
+    M_KEEP = 24, M_SLOT = 24, M_XCD = 30, M_SPENT = 31
 };
+// Header of a prepared run table (persistent schedule): its pair, its item
+// count with the flags of a query answered with padding, postings scanned.
+enum : uint32_t { H_PAIR = 0, H_S = 1, H_SCANNED = 2, H_WORDS = 3 };
+constexpr uint32_t kNoPair = 0xFFFFFFFFu;
+constexpr uint32_t kTooManyFlag = 1u << 30, kBadOffsetsFlag = 1u << 31;
+
+// The run of item `it` (dim, lo, hi) in tile t: [b, e) in padded elements
+// of the tile, with `pads` padding elements inside.  The keywords of one
+// dim are adjacent in the tile (Section 3.2, Position Map restricted to the
+// tile), so an item is the single run [off(dim*V+lo), off(dim*V+hi+1)); each
+// keyword's offset and its count of padded runs before it sit in one 8-byte
+// pair, so an item's two endpoints cost one or two 8-byte reads.
+__device__ __forceinline__ void item_run(const ScanParams &p, const uint2 *xrow, uint32_t t,
+                                         const uint32_t *it, uint32_t &b, uint32_t &e,
+                                         uint32_t &pads) {
+    uint32_t dim = it[0], lo = it[1], hi = it[2];
+    b = e = pads = 0;
+    if (dim >= p.d) {
+        if (t == 0)
+            atomicOr(p.status, GENIE_STATUS_BAD_DIM);
+    } else {
+        hi = min(hi, p.V - 1);
+        if (p.key_sets && lo < hi) {
+            // an object holds a keyword at most once, so one keyword per
+            // item keeps every count at most the number of items
+            if (t == 0)
+                atomicOr(p.status, GENIE_STATUS_RANGE_ON_SET);
+        } else if (lo <= hi) {
+            const uint64_t key = (uint64_t)dim * p.V;
+            const uint2 x0 = xrow[key + lo], x1 = xrow[key + hi + 1];
+            b = x0.x;
+            e = x1.x;
+            pads = x1.y - x0.y;
+        }
+    }
+}
 
 __device__ __forceinline__ uint32_t ht_home(uint32_t lid, uint32_t lg) {
     return (lid * 2654435761u) >> (32 - lg);
@@ -280,6 +319,79 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wave_sums, uint32
     return before + incl - v;
 }
 
+// Persistent schedule: the next pair of this workgroup, from the per-XCD
+// pair counters (one device-scope atomic per pair): the workgroup's own
+// XCD slice first, then the others in turn.  Called by one lane; the cursor
+// lives in LDS (misc M_XCD, M_SPENT).
+__device__ uint32_t claim_pair(const ScanParams &p, uint32_t *misc) {
+    const uint64_t npairs = (uint64_t)p.nq * p.n_tiles;
+    uint32_t x = misc[M_XCD], spent = misc[M_SPENT], pair = kNoPair;
+    while (spent < 8) {
+        const uint32_t idx = atomicAdd(&p.work[x], 1u);
+        const uint64_t first = (uint64_t)x * p.per_xcd;
+        const uint64_t slice = first >= npairs ? 0 : min<uint64_t>(p.per_xcd, npairs - first);
+        if (idx < slice) {
+            pair = (uint32_t)(first + idx);
+            if (p.qcount && pair % p.nq >= *p.qcount) {
+                pair = kNoPair;   // a row past the live count: take the next pair
+                continue;
+            }
+            break;
+        }
+        x = (x + 1) & 7;
+        spent++;
+    }
+    misc[M_XCD] = x;
+    misc[M_SPENT] = spent;
+    return pair;
+}
+
+// One wave claims the workgroup's next pair and builds its run table into a
+// slot (run starts sp_dw, prefix dword counts sp_cum, header hdr), 64 items
+// per round with a wave prefix sum.  Every lane of the wave must be active.
+__device__ void prepare_pair(const ScanParams &p, uint32_t *misc, uint32_t *sp_dw,
+                             uint32_t *sp_cum, uint32_t *hdr) {
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t pair = 0;
+    if (lane == 0)
+        pair = claim_pair(p, misc);
+    pair = __builtin_amdgcn_readfirstlane(pair);
+    if (pair == kNoPair) {
+        if (lane == 0)
+            hdr[H_PAIR] = kNoPair;
+        return;
+    }
+    const uint32_t t = pair / p.nq, q = pair % p.nq;
+    const uint64_t i0 = p.q_off[q], i1 = p.q_off[q + 1];
+    const bool bad_offsets = i1 < i0 || i1 > p.n_items;
+    const uint64_t s64 = bad_offsets ? 0 : i1 - i0;
+    const bool too_many = bad_offsets || s64 > p.max_items;
+    const uint32_t s = too_many ? 0 : (uint32_t)s64;
+    const uint2 *xrow = p.tix + (uint64_t)t * p.nkeys1;
+    uint32_t carry = 0, scanned = 0;
+    for (uint32_t c = 0; c < s; c += 64) {
+        const uint32_t i = c + lane;
+        uint32_t b = 0, e = 0, pads = 0;
+        if (i < s)
+            item_run(p, xrow, t, p.items + 3 * (i0 + i), b, e, pads);
+        const uint32_t dw = (e - b) >> 1;
+        const uint32_t incl = wave_inclusive_sum(dw);
+        if (i < s) {
+            sp_dw[i] = b >> 1;
+            sp_cum[i] = carry + incl - dw;
+        }
+        carry += __builtin_amdgcn_readlane(incl, 63);
+        scanned += (e - b) - pads;
+    }
+    scanned = __builtin_amdgcn_readlane(wave_inclusive_sum(scanned), 63);
+    if (lane == 0) {
+        sp_cum[s] = carry;
+        hdr[H_PAIR] = pair;
+        hdr[H_S] = s | (too_many ? kTooManyFlag : 0u) | (bad_offsets ? kBadOffsetsFlag : 0u);
+        hdr[H_SCANNED] = scanned;
+    }
+}
+
 // Occupancy: when the counters take at most 64 KB of LDS (2^LG counters of
 // BITS bits), the workgroup's LDS (counters plus the gate, queues and
 // table) lets two 1024-thread workgroups share a CU, i.e. 8 waves per SIMD,
@@ -293,10 +405,13 @@ constexpr int scan_waves_per_eu() {
 
 // One (query, tile) pair: the whole of Algorithm 1 over the tile's part of
 // the query's lists, then the tile's exact top-k.  `bc` is the workgroup's
-// static counter array; `smem` the dynamic LDS block.
-template <int BITS, int NT, int U, bool DUMP, int LG, bool SPQ = false>
+// static counter array; `smem` the dynamic LDS block.  PF (persistent
+// schedule): the pair's run table was prepared in run-table slot `slot`
+// while the workgroup's previous pair was counted, and the first wave to
+// finish counting this pair prepares the next one in the other slot.
+template <int BITS, int NT, int U, bool DUMP, int LG, bool SPQ = false, bool PF = false>
 __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, uint32_t *bc,
-                                          uint32_t *smem) {
+                                          uint32_t *smem, uint32_t slot = 0) {
     static_assert(BITS == 4 || BITS == 8 || BITS == 16, "power-of-two counter width");
     constexpr uint32_t CPW = 32 / BITS;                   // counters per word
     constexpr uint32_t LBITS = BITS == 4 ? 2 : (BITS == 8 ? 3 : 4);  // log2(BITS)
@@ -312,11 +427,19 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     uint32_t *ht = smem + 32;
     uint32_t *za = ht + cap;
     // run table: first dword of each item's run (tile-relative) and the
-    // prefix counts of the runs' dwords
-    uint32_t *sp_dw = za + (p.max_items + 2);
+    // prefix counts of the runs' dwords (two slots in the persistent schedule)
+    const uint32_t table_words = 2 * p.max_items + 1;
+    uint32_t *tables = za + (p.max_items + 2);
+    uint32_t *sp_dw = tables + (PF ? slot * table_words : 0u);
     uint32_t *sp_cum = sp_dw + p.max_items;               // max_items + 1 entries
     // per-wave queue of (count << 16 | local id) pairs that passed the gate
-    uint32_t *gq = sp_cum + p.max_items + 1 + ((threadIdx.x >> 6) * kGateQueue);
+    uint32_t *gq = tables + (PF ? 2u : 1u) * table_words + ((threadIdx.x >> 6) * kGateQueue);
+    // the next pair's table (persistent schedule), prepared by one wave
+    auto prepare_next = [&]() {
+        const uint32_t nslot = slot ^ 1u;
+        uint32_t *ndw = tables + nslot * table_words;
+        prepare_pair(p, misc, ndw, ndw + p.max_items, misc + M_SLOT + nslot * H_WORDS);
+    };
 
     const uint32_t t = (uint32_t)(pair / p.nq);
     const uint32_t qrow = (uint32_t)(pair % p.nq);
@@ -327,11 +450,22 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
 
     const uint64_t tile0 = (uint64_t)t * TILE;
     const uint32_t tile_n = (uint32_t)min<uint64_t>(TILE, p.n - tile0);
-    const uint64_t i0 = p.q_off[q], i1 = p.q_off[q + 1];
-    const bool bad_offsets = i1 < i0 || i1 > p.n_items;
-    const uint64_t s64 = bad_offsets ? 0 : i1 - i0;
-    const bool too_many = bad_offsets || s64 > p.max_items;
-    const uint32_t s = too_many ? 0 : (uint32_t)s64;
+    bool bad_offsets, too_many;
+    uint32_t s;
+    uint64_t i0 = 0;
+    if constexpr (PF) {   // from the prepared slot's header
+        const uint32_t hs = misc[M_SLOT + slot * H_WORDS + H_S];
+        bad_offsets = (hs & kBadOffsetsFlag) != 0;
+        too_many = (hs & kTooManyFlag) != 0;
+        s = hs & 0xFFFFu;
+    } else {
+        i0 = p.q_off[q];
+        const uint64_t i1 = p.q_off[q + 1];
+        bad_offsets = i1 < i0 || i1 > p.n_items;
+        const uint64_t s64 = bad_offsets ? 0 : i1 - i0;
+        too_many = bad_offsets || s64 > p.max_items;
+        s = too_many ? 0 : (uint32_t)s64;
+    }
 
     for (uint32_t i = tid; i < NW; i += NT)
         bc[i] = 0;
@@ -346,41 +480,21 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         const float g = fminf(p.gate[q] - p.gate_delta, (float)(s + 1));
         at0 = g >= 2.0f ? (uint32_t)floorf(g) : 1u;   // NaN and low values give 1
     }
-    if (tid < 32)
-        misc[tid] = (tid == M_AT) ? at0 : 0u;
-    // Position Map lookup (Section 3.2), restricted to this tile: the keywords
-    // of one dim are adjacent, so item (dim, lo, hi) is the single run
-    // [off[dim*V+lo], off[dim*V+hi+1]) of the tile (padded to whole dwords);
-    // each keyword's offset and its count of padded runs before it sit in one
-    // pair, so an item's two endpoints cost one or two 8-byte reads.
-    // The lookup writes only the run table (the counters are cleared
-    // meanwhile); a thread's share of the scanned postings reaches misc
-    // after a barrier.
+    // misc words from M_KEEP up hold the persistent schedule's state
+    if (tid < M_KEEP)
+        misc[tid] = (tid == M_AT) ? at0 : (PF && tid == M_SCANNED)
+                                              ? misc[M_SLOT + slot * H_WORDS + H_SCANNED] : 0u;
+    // Position Map lookup (Section 3.2), restricted to this tile, item by
+    // item (item_run).  The lookup writes only the run table (the counters
+    // are cleared meanwhile); a thread's share of the scanned postings
+    // reaches misc after a barrier.  A prepared pair has its table already.
     const uint2 *xrow = p.tix + (uint64_t)t * p.nkeys1;
     auto lookup = [&](uint32_t i, uint32_t &b, uint32_t &e, uint32_t &pads) {
-        const uint32_t *it = p.items + 3 * (i0 + i);
-        uint32_t dim = it[0], lo = it[1], hi = it[2];
-        b = e = pads = 0;
-        if (dim >= p.d) {
-            if (t == 0)
-                atomicOr(p.status, GENIE_STATUS_BAD_DIM);
-        } else {
-            hi = min(hi, p.V - 1);
-            if (p.key_sets && lo < hi) {
-                // an object holds a keyword at most once, so one keyword per
-                // item keeps every count at most the number of items
-                if (t == 0)
-                    atomicOr(p.status, GENIE_STATUS_RANGE_ON_SET);
-            } else if (lo <= hi) {
-                const uint64_t key = (uint64_t)dim * p.V;
-                const uint2 x0 = xrow[key + lo], x1 = xrow[key + hi + 1];
-                b = x0.x;
-                e = x1.x;
-                pads = x1.y - x0.y;
-            }
-        }
+        item_run(p, xrow, t, p.items + 3 * (i0 + i), b, e, pads);
     };
-    if (s <= 64) {
+    if (PF) {
+        __syncthreads();
+    } else if (s <= 64) {
         // one item per lane of wave 0 and a wave prefix sum of the runs'
         // dwords: the run table needs no barrier of its own
         if (tid < 64) {
@@ -443,6 +557,8 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                 p.pair_stats[row] = make_uint4(0u, 0u, 0u, 0u);
             }
         }
+        if (PF && tid < 64)
+            prepare_next();
         return;
     }
 
@@ -640,6 +756,15 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
         }
     if (lane == 0 && passes)
         lds_add(&misc[M_PASSES], passes);
+    if constexpr (PF) {
+        // the first wave to finish counting prepares the next pair (its
+        // loads overlap the counting of the waves still running)
+        uint32_t first = 1;
+        if (lane == 0)
+            first = lds_add(&misc[M_PREFETCH], 1u);
+        if (__builtin_amdgcn_readfirstlane(first) == 0)
+            prepare_next();
+    }
     __syncthreads();
     uint32_t spq_thr = 0;
     if constexpr (SPQ) {
@@ -843,24 +968,25 @@ void scan_cpq_kernel(ScanParams p) {
         // Persistent schedule: as many workgroups as fit the device at once,
         // each taking the next pair of its XCD's slice from that slice's
         // counter (one atomic per pair), then helping the other slices in
-        // turn.  Every workgroup leaves once all eight counters have run
-        // past their slices.
-        __shared__ uint32_t s_next;
-        uint32_t x = bid & 7;
-        for (uint32_t spent = 0; spent < 8;) {
-            if (threadIdx.x == 0)
-                s_next = atomicAdd(&p.work[x], 1u);
-            __syncthreads();
-            const uint64_t idx = s_next;
-            __syncthreads();
-            const uint64_t first = (uint64_t)x * p.per_xcd;
-            const uint64_t slice = first >= npairs ? 0 : min<uint64_t>(p.per_xcd, npairs - first);
-            if (idx >= slice) {
-                x = (x + 1) & 7;
-                spent++;
-                continue;
-            }
-            scan_pair<BITS, NT, U, DUMP, LG, SPQ>(p, first + idx, bc, smem);
+        // turn (claim_pair).  A pair's claim and run table are prepared while
+        // the workgroup still counts the pair before it, in the other of two
+        // run-table slots.  Every workgroup leaves once all eight counters
+        // have run past their slices.
+        (void)npairs;
+        if (threadIdx.x == 0) {
+            smem[M_XCD] = bid & 7;
+            smem[M_SPENT] = 0;
+        }
+        __syncthreads();
+        uint32_t *tables = smem + 32 + (1u << p.ht_log2) + (p.max_items + 2);
+        if (threadIdx.x < 64)
+            prepare_pair(p, smem, tables, tables + p.max_items, smem + M_SLOT);
+        __syncthreads();
+        for (uint32_t slot = 0;; slot ^= 1u) {
+            const uint32_t pair = smem[M_SLOT + slot * H_WORDS + H_PAIR];
+            if (pair == kNoPair)
+                break;
+            scan_pair<BITS, NT, U, DUMP, LG, SPQ, true>(p, pair, bc, smem, slot);
             __syncthreads();   // the next pair reuses the LDS
         }
     }
@@ -1018,6 +1144,7 @@ __global__ __launch_bounds__(NT) void merge_kernel(MergeParams p) {
 // Status block: flags, statistics, the fallback count and the persistent
 // schedule's pair counters (words 16..23; words 24..31 are spare).
 constexpr uint32_t kStatusWords = 32;
+constexpr uint64_t kPersistentMinPairs = 1024;   // below: one workgroup per pair
 constexpr uint32_t kWorkWord = 16;
 __global__ void clear_status_kernel(uint32_t *status) {
     if (threadIdx.x < kStatusWords)
@@ -1177,7 +1304,24 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     SearchShape shape;
     // the count dump and the GEN-SPQ ablation run 1024 x 4
     const int threads = (dump || spq) ? 1024 : ix->scan_threads;
-    int rc = search_shape(max_items, k, threads, ix->tile_log2, &shape, ix->ht_log2_cap);
+    // the persistent schedule keeps a second run table in LDS; where that
+    // does not fit, the search runs one workgroup per pair instead.  A
+    // search over a device row count (graph replay at a fixed capacity) also
+    // runs one workgroup per pair: the pairs of rows past the count exit at
+    // once there, while persistent workgroups would claim every one of them
+    // through the device counters.  Under the automatic schedule (2), so
+    // does a batch of fewer pairs than about two rounds of resident
+    // workgroups, where a workgroup would count one pair and gain nothing
+    // from preparing the next.
+    bool persistent = ix->scan_persistent && !dump && !spq && !d_rows &&
+                      (ix->scan_persistent == 1 ||
+                       (uint64_t)n_queries * ix->n_tiles >= kPersistentMinPairs);
+    int rc = search_shape(max_items, k, threads, ix->tile_log2, &shape, ix->ht_log2_cap,
+                          persistent);
+    if (rc && persistent) {
+        persistent = false;
+        rc = search_shape(max_items, k, threads, ix->tile_log2, &shape, ix->ht_log2_cap);
+    }
     if (rc)
         return rc;
     char *ws = static_cast<char *>(d_workspace);
@@ -1211,7 +1355,7 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     sp.gate = d_gate;
     sp.gate_delta = gate_delta;
     sp.spq = spq ? 1u : 0u;
-    sp.work = (ix->scan_persistent && !dump && !spq) ? sp.status + kWorkWord : nullptr;
+    sp.work = persistent ? sp.status + kWorkWord : nullptr;
     sp.qcount = d_rows;   // live rows (device), or null: all n_queries
     const uint64_t grid = sp.per_xcd * 8;
     if (grid > 0x7FFFFFFFull) {

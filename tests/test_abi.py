@@ -180,7 +180,7 @@ def test_probe_argument_errors_without_device():
     lib = genie.load()
     # probes: bad mode, zero sizes, null outputs
     out = ctypes.c_double()
-    assert lib.genie_probe_lds_atomics(3, 1, 1, None, ctypes.byref(out)) == genie.GENIE_EINVAL
+    assert lib.genie_probe_lds_atomics(4, 1, 1, None, ctypes.byref(out)) == genie.GENIE_EINVAL
     assert lib.genie_probe_lds_atomics(0, 0, 1, None, ctypes.byref(out)) == genie.GENIE_EINVAL
     assert lib.genie_probe_hbm(None, None, 1 << 20, 1, None, ctypes.byref(out),
                                None) == genie.GENIE_EINVAL

@@ -77,12 +77,17 @@ def test_tiny_workload_full():
     _check(inst.values, inst.V, inst.queries, inst.k)
 
 
+@pytest.mark.parametrize("schedule", [1, 0])
 @pytest.mark.parametrize("k", [1, 7, 100, 1000])
-def test_relational_several_tiles_ragged(k):
-    # 3 full tiles and a ragged fourth one
+def test_relational_several_tiles_ragged(k, schedule):
+    # 3 full tiles and a ragged fourth one; persistent workgroups and one
+    # workgroup per pair
     inst = workloads.relational(n=3 * 65536 + 1234, d=8, V=32, nq=48, k=k)
-    print("relational scaled", inst.n, inst.d, k, flush=True)
-    _check(inst.values, inst.V, inst.queries, k)
+    print("relational scaled", inst.n, inst.d, k, "schedule", schedule, flush=True)
+    ix = genie.Index(inst.values, inst.V)
+    genie.genie_index_set_scan_schedule(ix, schedule)
+    _check(inst.values, inst.V, inst.queries, k, ix=ix)
+    ix.free()
 
 
 def test_uneven_items_scaled():
@@ -240,11 +245,12 @@ def test_sync_host_entry_point_and_errors():
 def test_relational_full_size_every_row():
     """1,000,000 x 32, Zipf(1.1) over 256 buckets, 1,024 queries, k = 100: the
     whole batch in one call (the benchmark's launch: tiles of 65,535 objects,
-    1024 x 4, one workgroup per pair), every row against the oracle."""
+    1024 x 4, persistent workgroups), every row against the oracle, and the
+    same batch with one workgroup per pair."""
     inst = workloads.relational()
     print("relational full", inst.n, inst.d, inst.queries.n_queries, flush=True)
     ix = genie.Index(inst.values, inst.V)
-    assert ix.info.scan_shape == (1024, 4) and ix.info.scan_persistent == 0
+    assert ix.info.scan_shape == (1024, 4) and ix.info.scan_persistent == 2
     ids, cts, st = _run(ix, inst.queries, inst.k)
     assert st["status"] == 0, st
     o_ids, o_cts, scanned = oracle_rows(inst.values, inst.V, inst.queries, inst.k)
@@ -252,6 +258,10 @@ def test_relational_full_size_every_row():
     bad = np.nonzero((ids != o_ids).any(axis=1) | (cts != o_cts).any(axis=1))[0]
     assert len(bad) == 0, f"{len(bad)} of 1024 rows differ, first {bad[0]}"
     print("stats", st, flush=True)
+    genie.genie_index_set_scan_schedule(ix, 0)
+    ids, cts, st = _run(ix, inst.queries, inst.k)
+    assert st["status"] == 0 and st["postings_scanned"] == int(scanned.sum())
+    assert np.array_equal(ids, o_ids) and np.array_equal(cts, o_cts)
     ix.free()
 
 
