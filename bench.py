@@ -131,7 +131,8 @@ def measure_peaks(genie) -> dict:
     log("probing LDS atomic and HBM peaks")
     peaks = {"lds_atomic_conflict_free": genie.genie_probe_lds_atomics(0),
              "lds_atomic_random": genie.genie_probe_lds_atomics(1),
-             "lds_atomic_random_no_return": genie.genie_probe_lds_atomics(2)}
+             "lds_atomic_random_no_return": genie.genie_probe_lds_atomics(2),
+             "lds_atomic_one_bank_per_lane": genie.genie_probe_lds_atomics(3)}
     rd, cp = genie.genie_probe_hbm(2 << 30, 5)
     peaks.update(hbm_read_gbs=round(rd, 1), hbm_copy_gbs=round(cp, 1),
                  hbm_spec_gbs=HBM_PEAK_GBS,
@@ -149,10 +150,14 @@ def roofs(scanned, s_total, nq, k, n_tiles, kernel_ms, peaks, traffic):
     the bytes this layout reads (2 B per posting, 12 B per item, 8 B of
     Position Map per item and tile, 8 B per result) and the HBM bytes the
     counters measured.  LDS atomics: one increment per posting, against the
-    measured conflict-free rate of LDS atomic adds with return.  When the
-    algorithmic bytes arrive faster than HBM can deliver them, the index is
-    served from the caches and HBM cannot be the bound; otherwise the roof
-    with the larger fraction binds."""
+    measured conflict-free rate of LDS atomic adds with return (lanes on
+    consecutive words); beside it the fraction of the rate measured when
+    each lane hits its own bank at scattered rows, which is what a scan's
+    addresses look like (about half the conflict-free rate).  When the
+    algorithmic bytes arrive faster than HBM can deliver them (the layout
+    moves 2 B per posting and the caches serve part of them), HBM cannot be
+    the bound in these bytes; otherwise the roof with the larger fraction
+    binds."""
     t = kernel_ms * 1e-3
     alg = 4 * scanned + 12 * s_total + 16 * s_total + 8 * k * nq
     layout = 2 * scanned + 12 * s_total + 8 * s_total * n_tiles + 8 * k * nq
@@ -175,8 +180,11 @@ def roofs(scanned, s_total, nq, k, n_tiles, kernel_ms, peaks, traffic):
                hbm_alg_frac=round(hbm_frac, 4),
                layout_bytes_per_launch=layout,
                hbm_measured_gbs=(round(traffic / t / 1e9, 1) if traffic else None),
+               hbm_measured_frac=(round(traffic / t / 1e9 / HBM_PEAK_GBS, 4) if traffic else None),
                lds_atomic_rate=round(rate / 1e9, 1), lds_atomic_frac=round(lds_frac, 4),
                lds_atomic_frac_of_random=round(rate / peaks["lds_atomic_random"], 4),
+               lds_atomic_frac_of_one_bank_per_lane=round(
+                   rate / peaks["lds_atomic_one_bank_per_lane"], 4),
                postings_per_launch=scanned)
     return out
 
