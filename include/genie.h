@@ -83,6 +83,10 @@ typedef struct {
     uint32_t scan_threads;     /* scan kernel launch shape in use (see */
     uint32_t scan_unroll;      /* genie_index_set_scan_shape) */
     uint32_t scan_persistent;  /* schedule 0, 1 or 2 (genie_index_set_scan_schedule) */
+    uint32_t map_compact;      /* 1: Position Map in the compact form (3 bytes per tile
+                                  and keyword, chosen where the 8-byte form would
+                                  exceed a quarter of the postings' bytes) */
+    uint64_t map_bytes;        /* device bytes of the Position Map */
 } genie_index_info;
 
 /*

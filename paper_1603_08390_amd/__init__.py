@@ -86,7 +86,8 @@ class _IndexInfo(ctypes.Structure):
                 ("n_buckets", ctypes.c_uint32), ("n_tiles", ctypes.c_uint32),
                 ("tile_objects", ctypes.c_uint32), ("n_postings", ctypes.c_uint64),
                 ("device_bytes", ctypes.c_uint64), ("scan_threads", ctypes.c_uint32),
-                ("scan_unroll", ctypes.c_uint32), ("scan_persistent", ctypes.c_uint32)]
+                ("scan_unroll", ctypes.c_uint32), ("scan_persistent", ctypes.c_uint32),
+                ("map_compact", ctypes.c_uint32), ("map_bytes", ctypes.c_uint64)]
 
 
 _lib = None
@@ -233,6 +234,8 @@ class IndexInfo:
     device_bytes: int
     scan_shape: tuple      # (threads per workgroup, posting dwords per thread and step)
     scan_persistent: int   # 0: one workgroup per (query, tile) pair; 1: persistent; 2: auto
+    map_compact: int = 0   # 1: Position Map in the compact form
+    map_bytes: int = 0     # device bytes of the Position Map
 
 
 class Index:
@@ -256,7 +259,8 @@ class Index:
         _check(load().genie_index_info_get(self.handle, ctypes.byref(info)))
         self.info = IndexInfo(info.n_objects, info.n_dims, info.n_buckets, info.n_tiles,
                               info.tile_objects, info.n_postings, info.device_bytes,
-                              (info.scan_threads, info.scan_unroll), info.scan_persistent)
+                              (info.scan_threads, info.scan_unroll), info.scan_persistent,
+                              info.map_compact, info.map_bytes)
 
     @property
     def handle(self):

@@ -353,6 +353,34 @@ void interleave_offsets(const HostIndex &h, uint32_t *dst) {
     }
 }
 
+void write_offsets(const HostIndex &h, uint8_t *dst) {
+    if (use_compact_map(h))
+        compact_offsets(h, dst);
+    else
+        interleave_offsets(h, reinterpret_cast<uint32_t *>(dst));
+}
+
+void compact_offsets(const HostIndex &h, uint8_t *dst) {
+    const uint64_t T = h.n_tiles, K = h.nkeys, G = map_groups(K);
+    uint32_t *ck = reinterpret_cast<uint32_t *>(dst);
+    uint16_t *ln = reinterpret_cast<uint16_t *>(dst + map_ck_bytes(T, K));
+    std::memset(dst, 0, map_bytes(T, K));
+    for (uint64_t t = 0; t < T; t++) {
+        const uint32_t *row = &h.toff[t * (K + 1)];
+        const uint32_t *prow = &h.tpad[t * (K + 1)];
+        for (uint64_t g = 0; g < G; g++) {
+            const uint64_t k0 = g * kMapGroup;   // <= K
+            ck[2 * (t * G + g)] = row[k0];
+            ck[2 * (t * G + g) + 1] = prow[k0];
+            for (uint64_t r = 0; r < kMapGroup && k0 + r < K; r++) {
+                const uint64_t key = k0 + r;
+                ln[(t * G + g) * kMapGroup + r] =
+                    (uint16_t)((row[key + 1] - row[key]) - (prow[key + 1] - prow[key]));
+            }
+        }
+    }
+}
+
 int upload_host_index(const HostIndex &h, genie_index **out) {
     const uint32_t T = h.n_tiles;
     genie_index *ix = new (std::nothrow) genie_index;
@@ -372,7 +400,9 @@ int upload_host_index(const HostIndex &h, genie_index **out) {
     ix->key_sets = h.key_sets;
     hipError_t e = hipGetDevice(&ix->device);
     size_t bp = h.post.size() * sizeof(uint16_t), bb = h.tile_base.size() * sizeof(uint64_t),
-           bt = 2 * h.toff.size() * sizeof(uint32_t), bk = h.kcum.size() * sizeof(uint64_t);
+           bt = device_map_bytes(h), bk = h.kcum.size() * sizeof(uint64_t);
+    ix->map_compact = use_compact_map(h);
+    ix->map_bytes = bt;
     if (e == hipSuccess) e = hipMalloc((void **)&ix->post, bp);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->tile_base, bb);
     if (e == hipSuccess) e = hipMalloc((void **)&ix->tix, bt);
@@ -381,15 +411,15 @@ int upload_host_index(const HostIndex &h, genie_index **out) {
     if (e == hipSuccess) e = hipMemcpy(ix->post, h.post.data(), bp, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ix->tile_base, h.tile_base.data(), bb, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        std::vector<uint32_t> tix;
+        std::vector<uint8_t> tix;
         try {
-            tix.resize(2 * h.toff.size());
+            tix.resize(bt);
         } catch (const std::bad_alloc &) {
             set_error("out of host memory for the index offsets");
             genie_free_index(ix);
             return GENIE_ENOMEM;
         }
-        interleave_offsets(h, tix.data());
+        write_offsets(h, tix.data());
         e = hipMemcpy(ix->tix, tix.data(), bt, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
@@ -506,6 +536,8 @@ extern "C" int genie_index_info_get(const genie_index *ix, genie_index_info *out
     out->scan_threads = (uint32_t)ix->scan_threads;
     out->scan_unroll = (uint32_t)ix->scan_unroll;
     out->scan_persistent = (uint32_t)ix->scan_persistent;
+    out->map_compact = ix->map_compact ? 1u : 0u;
+    out->map_bytes = ix->map_bytes;
     return GENIE_OK;
 }
 

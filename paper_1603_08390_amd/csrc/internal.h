@@ -44,9 +44,13 @@ struct genie_index {
     // device arrays
     uint16_t *post = nullptr;      // tile-major, keyword-major, ascending local ids (+ pad)
     uint64_t *tile_base = nullptr; // n_tiles + 1 element offsets of each tile in post
-    // n_tiles rows of nkeys + 1 pairs {padded offset relative to tile_base,
-    // padded runs before the keyword}: one lookup reads both from one line
-    uint32_t *tix = nullptr;
+    // Position Map per tile (offsets relative to tile_base): n_tiles rows of
+    // nkeys + 1 pairs {padded offset, padded runs before} (one 8-byte read per
+    // lookup), or, where that would exceed a quarter of the postings' bytes,
+    // the compact form of compact_offsets (3 bytes per keyword)
+    uint8_t *tix = nullptr;
+    bool map_compact = false;
+    uint64_t map_bytes = 0;
     uint64_t *kcum = nullptr;      // nkeys + 1 prefix counts of postings per keyword (all tiles)
     uint64_t stored_postings = 0;  // elements in post (real + padding + trailing sentinels)
     uint64_t device_bytes = 0;
@@ -78,9 +82,41 @@ int build_host_index(const uint32_t *values, uint64_t n, uint32_t d, uint32_t V,
 int build_host_index_sets(const uint64_t *obj_offsets, const uint32_t *keys, uint64_t n,
                           uint32_t n_keys, uint32_t tile_log2, HostIndex *h);
 int upload_host_index(const HostIndex &h, genie_index **out);
-// Writes the device form of h's offset rows: 2 * h.toff.size() words,
-// {toff[i], tpad[i]} at 2i and 2i + 1.
+
+// Device form of the Position Map (Section 3.2), restricted per tile: for
+// each tile, keywords 0..nkeys in groups of 8, each group one 8-byte
+// checkpoint {padded offset, padded runs before} of its first keyword and
+// one 16-byte record of the 8 keywords' real run lengths (uint16: a tile
+// holds fewer than 2^16 objects, each at most once per keyword).  A
+// keyword's offset is its group's checkpoint plus the padded lengths of the
+// keywords before it in the group.  3 bytes per (tile, keyword) instead of
+// 8.  Layout: checkpoints of every tile's groups (padded to 16 bytes), then
+// the length records.
+constexpr uint64_t kMapGroup = 8;
+inline uint64_t map_groups(uint64_t nkeys) { return nkeys / kMapGroup + 1; }
+inline size_t map_ck_bytes(uint64_t n_tiles, uint64_t nkeys) {
+    return (size_t)((n_tiles * map_groups(nkeys) * 8 + 15) & ~uint64_t(15));
+}
+inline size_t map_bytes(uint64_t n_tiles, uint64_t nkeys) {
+    return map_ck_bytes(n_tiles, nkeys) + (size_t)(n_tiles * map_groups(nkeys) * 16);
+}
+// Writes h's Position Map in that device form (map_bytes(n_tiles, nkeys)).
+void compact_offsets(const HostIndex &h, uint8_t *dst);
+// The 8-byte form: n_tiles * (nkeys + 1) pairs {toff[i], tpad[i]}.
 void interleave_offsets(const HostIndex &h, uint32_t *dst);
+inline size_t full_map_bytes(uint64_t n_tiles, uint64_t nkeys) {
+    return (size_t)(n_tiles * (nkeys + 1) * 8);
+}
+// The form an index uses: compact where the 8-byte form would exceed a
+// quarter of the postings' bytes.
+inline bool use_compact_map(const HostIndex &h) {
+    return full_map_bytes(h.n_tiles, h.nkeys) * 4 > h.post.size() * sizeof(uint16_t);
+}
+inline size_t device_map_bytes(const HostIndex &h) {
+    return use_compact_map(h) ? map_bytes(h.n_tiles, h.nkeys) : full_map_bytes(h.n_tiles, h.nkeys);
+}
+// Writes h's Position Map in the form use_compact_map picks.
+void write_offsets(const HostIndex &h, uint8_t *dst);
 
 void set_error(const char *fmt, ...);
 void clear_error();
@@ -131,7 +167,8 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
 struct IndexView {
     const uint16_t *post = nullptr;
     const uint64_t *tile_base = nullptr;
-    const uint32_t *tix = nullptr;   // offset pairs, as in genie_index
+    const uint8_t *tix = nullptr;   // Position Map, as in genie_index
+    bool map_compact = false;
     uint64_t n = 0, nkeys = 0;
     uint32_t d = 0, V = 0, n_tiles = 0, tile_log2 = 0;
     int scan_threads = kScanThreadsDefault, scan_unroll = kScanUnrollDefault;

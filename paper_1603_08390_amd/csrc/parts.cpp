@@ -27,14 +27,15 @@ struct PartHost {
     uint64_t nkeys = 0;
     uint16_t *post = nullptr;       // pinned host arrays of the part's index
     uint64_t *tile_base = nullptr;
-    uint32_t *tix = nullptr;        // offset pairs, as in genie_index
+    uint8_t *tix = nullptr;         // Position Map, as in genie_index
+    bool map_compact = false;
     size_t post_bytes = 0, base_bytes = 0, off_bytes = 0;
 };
 
 struct Slot {
     uint16_t *post = nullptr;
     uint64_t *tile_base = nullptr;
-    uint32_t *tix = nullptr;
+    uint8_t *tix = nullptr;
     hipEvent_t copied = nullptr, scanned = nullptr;
 };
 
@@ -114,7 +115,8 @@ extern "C" int genie_parts_build(const uint32_t *values, uint64_t n, uint32_t d,
         p.nkeys = h.nkeys;
         p.post_bytes = h.post.size() * sizeof(uint16_t);
         p.base_bytes = h.tile_base.size() * sizeof(uint64_t);
-        p.off_bytes = 2 * h.toff.size() * sizeof(uint32_t);
+        p.off_bytes = device_map_bytes(h);
+        p.map_compact = use_compact_map(h);
         // pinned host copies: the copies to the device run asynchronously
         e = hipHostMalloc((void **)&p.post, p.post_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&p.tile_base, p.base_bytes, hipHostMallocDefault);
@@ -125,7 +127,7 @@ extern "C" int genie_parts_build(const uint32_t *values, uint64_t n, uint32_t d,
         PartHost &q = ps->parts.back();
         std::memcpy(q.post, h.post.data(), q.post_bytes);
         std::memcpy(q.tile_base, h.tile_base.data(), q.base_bytes);
-        interleave_offsets(h, q.tix);
+        write_offsets(h, q.tix);
         ps->host_bytes += q.post_bytes + q.base_bytes + q.off_bytes;
         max_post = std::max(max_post, q.post_bytes);
         max_base = std::max(max_base, q.base_bytes);
@@ -231,6 +233,7 @@ extern "C" int genie_parts_search_async(genie_parts *ps, const uint64_t *d_q_off
         v.post = s.post;
         v.tile_base = s.tile_base;
         v.tix = s.tix;
+        v.map_compact = p.map_compact;
         v.n = p.n;
         v.nkeys = p.nkeys;
         v.d = ps->d;

@@ -26,9 +26,13 @@ namespace {
 struct ScanParams {
     const uint16_t *post;
     const uint64_t *tile_base;
-    const uint2 *tix;       // per tile, nkeys1 pairs {padded offset, padded runs before}
+    const uint2 *map_ck;    // Position Map: per tile, nkeys + 1 pairs {offset, pads}, or in
+                            // the compact form map_groups checkpoints {offset, pads}
+    const uint4 *map_len;   // ... and per group the 8 keywords' run lengths (uint16)
+    uint32_t map_compact;   // 1: the compact form
     uint64_t n;
-    uint64_t nkeys1;        // keywords + 1 (row length of tix)
+    uint64_t nkeys;         // keywords
+    uint64_t map_groups;    // Position Map groups per tile
     uint32_t d, V, n_tiles;
     const uint64_t *q_off;
     const uint32_t *items;  // 3 words per item
@@ -141,15 +145,43 @@ enum : uint32_t { H_PAIR = 0, H_S = 1, H_SCANNED = 2, H_WORDS = 3 };
 constexpr uint32_t kNoPair = 0xFFFFFFFFu;
 constexpr uint32_t kTooManyFlag = 1u << 30, kBadOffsetsFlag = 1u << 31;
 
+// Position Map entry of keyword `key` in tile t: {padded offset of its run
+// in the tile, padded runs before it}: one 8-byte read.  In the compact form
+// the map keeps one checkpoint per group of 8 keywords and the group's real
+// run lengths (uint16); the entry is the checkpoint plus the padded lengths
+// (and odd lengths) of the group's keywords before `key`: one 8-byte and
+// one 16-byte read.
+// `own` (compact form) receives the real run length of `key` itself.
+__device__ __forceinline__ uint2 map_entry(const ScanParams &p, uint32_t t, uint64_t key,
+                                           uint32_t *own = nullptr) {
+    if (!p.map_compact)
+        return p.map_ck[(uint64_t)t * (p.nkeys + 1) + key];
+    const uint64_t g = (uint64_t)t * p.map_groups + (key >> 3);
+    const uint2 c = p.map_ck[g];
+    const uint4 L = p.map_len[g];
+    const uint32_t r = (uint32_t)(key & 7);
+    const uint32_t w[4] = {L.x, L.y, L.z, L.w};
+    uint32_t off = c.x, pads = c.y, mine = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 8; j++) {
+        const uint32_t len = (w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu, odd = len & 1u;
+        if (j < r) {
+            off += len + odd;
+            pads += odd;
+        }
+        mine = j == r ? len : mine;
+    }
+    if (own)
+        *own = mine;
+    return make_uint2(off, pads);
+}
+
 // The run of item `it` (dim, lo, hi) in tile t: [b, e) in padded elements
 // of the tile, with `pads` padding elements inside.  The keywords of one
 // dim are adjacent in the tile (Section 3.2, Position Map restricted to the
-// tile), so an item is the single run [off(dim*V+lo), off(dim*V+hi+1)); each
-// keyword's offset and its count of padded runs before it sit in one 8-byte
-// pair, so an item's two endpoints cost one or two 8-byte reads.
-__device__ __forceinline__ void item_run(const ScanParams &p, const uint2 *xrow, uint32_t t,
-                                         const uint32_t *it, uint32_t &b, uint32_t &e,
-                                         uint32_t &pads) {
+// tile), so an item is the single run [off(dim*V+lo), off(dim*V+hi+1)).
+__device__ __forceinline__ void item_run(const ScanParams &p, uint32_t t, const uint32_t *it,
+                                         uint32_t &b, uint32_t &e, uint32_t &pads) {
     uint32_t dim = it[0], lo = it[1], hi = it[2];
     b = e = pads = 0;
     if (dim >= p.d) {
@@ -164,10 +196,17 @@ __device__ __forceinline__ void item_run(const ScanParams &p, const uint2 *xrow,
                 atomicOr(p.status, GENIE_STATUS_RANGE_ON_SET);
         } else if (lo <= hi) {
             const uint64_t key = (uint64_t)dim * p.V;
-            const uint2 x0 = xrow[key + lo], x1 = xrow[key + hi + 1];
-            b = x0.x;
-            e = x1.x;
-            pads = x1.y - x0.y;
+            if (p.map_compact && lo == hi) {   // one keyword: its own length ends the run
+                uint32_t len = 0;
+                b = map_entry(p, t, key + lo, &len).x;
+                e = b + len + (len & 1u);
+                pads = len & 1u;
+            } else {
+                const uint2 x0 = map_entry(p, t, key + lo), x1 = map_entry(p, t, key + hi + 1);
+                b = x0.x;
+                e = x1.x;
+                pads = x1.y - x0.y;
+            }
         }
     }
 }
@@ -367,13 +406,12 @@ __device__ void prepare_pair(const ScanParams &p, uint32_t *misc, uint32_t *sp_d
     const uint64_t s64 = bad_offsets ? 0 : i1 - i0;
     const bool too_many = bad_offsets || s64 > p.max_items;
     const uint32_t s = too_many ? 0 : (uint32_t)s64;
-    const uint2 *xrow = p.tix + (uint64_t)t * p.nkeys1;
     uint32_t carry = 0, scanned = 0;
     for (uint32_t c = 0; c < s; c += 64) {
         const uint32_t i = c + lane;
         uint32_t b = 0, e = 0, pads = 0;
         if (i < s)
-            item_run(p, xrow, t, p.items + 3 * (i0 + i), b, e, pads);
+            item_run(p, t, p.items + 3 * (i0 + i), b, e, pads);
         const uint32_t dw = (e - b) >> 1;
         const uint32_t incl = wave_inclusive_sum(dw);
         if (i < s) {
@@ -488,9 +526,8 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     // item (item_run).  The lookup writes only the run table (the counters
     // are cleared meanwhile); a thread's share of the scanned postings
     // reaches misc after a barrier.  A prepared pair has its table already.
-    const uint2 *xrow = p.tix + (uint64_t)t * p.nkeys1;
     auto lookup = [&](uint32_t i, uint32_t &b, uint32_t &e, uint32_t &pads) {
-        item_run(p, xrow, t, p.items + 3 * (i0 + i), b, e, pads);
+        item_run(p, t, p.items + 3 * (i0 + i), b, e, pads);
     };
     if (PF) {
         __syncthreads();
@@ -573,7 +610,8 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     // without a bounds test; lanes past the end read the tile's trailing
     // all-sentinel dwords.
     const char *tile_bytes = reinterpret_cast<const char *>(p.post) + 2 * p.tile_base[t];
-    const uint32_t sent_dw = xrow[p.nkeys1 - 1].x >> 1;   // trailing sentinel dwords of the tile
+    // the tile's trailing sentinel dwords start where the last keyword's run ends
+    const uint32_t sent_dw = map_entry(p, t, p.nkeys).x >> 1;
     const uint32_t k = p.k;
     // wave-uniform values, so that the run cursor lives in scalar registers
     const uint32_t total_dw = __builtin_amdgcn_readfirstlane(sp_cum[s]);
@@ -1236,9 +1274,12 @@ int launch_part_scan(const IndexView &v, uint64_t id_base, uint32_t tile_off,
     ScanParams sp{};
     sp.post = v.post;
     sp.tile_base = v.tile_base;
-    sp.tix = reinterpret_cast<const uint2 *>(v.tix);
+    sp.map_ck = reinterpret_cast<const uint2 *>(v.tix);
+    sp.map_len = reinterpret_cast<const uint4 *>(v.tix + map_ck_bytes(v.n_tiles, v.nkeys));
+    sp.map_groups = map_groups(v.nkeys);
+    sp.map_compact = v.map_compact ? 1u : 0u;
     sp.n = v.n;
-    sp.nkeys1 = v.nkeys + 1;
+    sp.nkeys = v.nkeys;
     sp.d = v.d;
     sp.V = v.V;
     sp.n_tiles = v.n_tiles;
@@ -1328,9 +1369,12 @@ int launch_search(const genie_index *ix, const uint64_t *d_q_offsets, const geni
     ScanParams sp{};
     sp.post = ix->post;
     sp.tile_base = ix->tile_base;
-    sp.tix = reinterpret_cast<const uint2 *>(ix->tix);
+    sp.map_ck = reinterpret_cast<const uint2 *>(ix->tix);
+    sp.map_len = reinterpret_cast<const uint4 *>(ix->tix + map_ck_bytes(ix->n_tiles, ix->nkeys));
+    sp.map_groups = map_groups(ix->nkeys);
+    sp.map_compact = ix->map_compact ? 1u : 0u;
     sp.n = ix->n;
-    sp.nkeys1 = ix->nkeys + 1;
+    sp.nkeys = ix->nkeys;
     sp.d = ix->d;
     sp.V = ix->V;
     sp.key_sets = ix->key_sets ? 1u : 0u;

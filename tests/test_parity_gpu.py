@@ -348,3 +348,32 @@ def test_gen_spq_ablation_equals_oracle(case):
     assert np.array_equal(genie.as_uint32(ids), o_ids)
     assert np.array_equal(genie.as_uint32(cts), o_cts)
     ix.free()
+
+
+@pytest.mark.parametrize("schedule", [1, 0])
+def test_compact_position_map(schedule):
+    """An index with many keywords per posting (4,096 buckets on 8 dims over
+    3 tiles and a ragged fourth) keeps its Position Map in the compact form
+    (checkpoints every 8 keywords plus uint16 run lengths); range items of up
+    to 41 keywords cross the 8-keyword groups.  Plain and gated answers
+    against the oracle."""
+    rng = np.random.default_rng(808)
+    n, d, V = 3 * 65535 + 999, 8, 4096
+    values = rng.integers(0, V, size=(n, d), dtype=np.uint32)
+    qs = workloads.queries_random_width(rng, values, V, 40, wmax=40)
+    ix = genie.Index(values, V)
+    assert ix.info.map_compact == 1
+    assert ix.info.map_bytes < ix.info.n_tiles * (d * V + 1) * 8 / 2
+    genie.genie_index_set_scan_schedule(ix, schedule)
+    print("compact map: schedule", schedule, ix.info, flush=True)
+    _check(values, V, qs, 100, ix=ix)
+    o_ids, o_cts, o_kth, _ = oracle.search_idx(oracle.build_csr(values, V), qs, 100)
+    off, items = genie.queries_to_device(qs.q_offsets, qs.items)
+    pred = torch.from_numpy(o_kth.astype(np.float32)).cuda()
+    g_ids, g_cts, ws = genie.genie_search_gated_async(ix, off, items, 100, qs.max_items(), pred,
+                                                      0.0)
+    torch.cuda.synchronize()
+    assert genie.workspace_stats(ws)["status"] == 0
+    assert np.array_equal(genie.as_uint32(g_ids), o_ids)
+    assert np.array_equal(genie.as_uint32(g_cts), o_cts)
+    ix.free()
