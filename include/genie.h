@@ -638,6 +638,9 @@ int genie_kernel_timing_read(genie_kernel_times *out, int reset);
  *   mode 2: without return, pseudo-random words;
  *   mode 3: with return, lane l at word l of a pseudo-random 64-word row
  *           (one bank per lane, rows scattered).
+ *   Modes 1-3 draw per-lane random words once and move them every step by
+ *   XOR with a step-dependent value shared by the wave (one vector op per
+ *   atomic), which keeps mode 3's lane-to-bank relation.
  *   d_sink: device, n_blocks * 1024 uint32 (written; keeps results live).
  *   *out_per_s: atomic adds per second over the chip (one untimed launch,
  *   then one timed by HIP events).

@@ -9,7 +9,11 @@
 //    words (conflict-free), returning adds at pseudo-random words of the 64 KB,
 //    non-returning adds at pseudo-random words, and returning adds where
 //    lane l hits word l of a pseudo-random 64-word row (every lane in its
-//    own bank, the rows scattered, as in a bank-ordered scan).
+//    own bank, the rows scattered, as in a bank-ordered scan).  Addresses
+//    cost one VALU op per atomic (per-lane random bases moved each step by
+//    a wave-uniform value), so the probe measures the LDS, not the address
+//    arithmetic (with a full hash per address the random modes ran at the
+//    VALU's rate).
 //  * HBM streaming rate: a read of a device buffer (16-byte loads, coalesced,
 //    grid-stride) and a copy into a second buffer.
 #include <hip/hip_runtime.h>
@@ -45,20 +49,29 @@ void lds_atomic_probe_kernel(uint32_t steps, uint32_t *sink) {
         buf[i] = 0;
     __syncthreads();
     uint32_t acc = 0;
-    uint32_t seed = mix32(blockIdx.x * kProbeThreads + tid);
+    // Per-lane bases drawn once; each step moves them by one wave-uniform
+    // value (a scalar mix of the step number, XORed in: one VALU op per
+    // atomic), so the probe is bound by the LDS, not by address arithmetic.
+    // XOR with a uniform value keeps each lane's bank in mode 3 and the
+    // pattern of bank collisions between lanes in modes 1 and 2.
+    const uint32_t seed = mix32(blockIdx.x * kProbeThreads + tid);
+    uint32_t base[kProbeBatch];
+#pragma unroll
+    for (int j = 0; j < kProbeBatch; j++) {
+        const uint32_t r = mix32(seed + (uint32_t)j * 0x9e3779b9u);
+        base[j] = MODE == 3 ? ((r << 6) | (tid & 63)) & (kProbeWords - 1) : r & (kProbeWords - 1);
+    }
     for (uint32_t s = 0; s < steps; s++) {
         uint32_t addr[kProbeBatch];
+        const uint32_t c = __builtin_amdgcn_readfirstlane(mix32(s * 0x632be5abu + 1u)) &
+                           (MODE == 3 ? (kProbeWords - 64) : (kProbeWords - 1));
 #pragma unroll
         for (int j = 0; j < kProbeBatch; j++) {
             if (MODE == 0)   // wave w, lane l: word 64 w + l of a 1024-word block
                 addr[j] = (tid + (uint32_t)j * kProbeThreads + s * 128u) & (kProbeWords - 1);
-            else if (MODE == 3)   // lane l: word l of a pseudo-random 64-word row
-                addr[j] = ((mix32(seed + (uint32_t)j * 0x9e3779b9u) << 6) | (tid & 63)) &
-                          (kProbeWords - 1);
             else
-                addr[j] = mix32(seed + (uint32_t)j * 0x9e3779b9u) & (kProbeWords - 1);
+                addr[j] = base[j] ^ c;
         }
-        seed += 0x632be5abu;
         if (MODE == 2) {
 #pragma unroll
             for (int j = 0; j < kProbeBatch; j++)

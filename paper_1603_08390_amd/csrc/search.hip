@@ -434,11 +434,14 @@ __device__ void prepare_pair(const ScanParams &p, uint32_t *misc, uint32_t *sp_d
 // BITS bits), the workgroup's LDS (counters plus the gate, queues and
 // table) lets two 1024-thread workgroups share a CU, i.e. 8 waves per SIMD,
 // if the kernel fits 64 VGPRs; the scan is bound by the latency of its loads
-// and LDS atomics, so that occupancy is asked for explicitly.  128 KB of
-// counters (16-bit counters over 2^16 ids) allow one workgroup per CU.
+// and LDS atomics, so that occupancy is asked for explicitly.  Likewise four
+// 512-thread workgroups with at most 32 KB of counters (8-bit counters over
+// 2^15 ids).  128 KB of counters (16-bit counters over 2^16 ids) allow one
+// workgroup per CU.
 template <int BITS, int NT, int LG>
 constexpr int scan_waves_per_eu() {
-    return (NT == 1024 && (BITS << LG) <= (8 << 16)) ? 8 : 1;
+    return ((NT == 1024 && (BITS << LG) <= (8 << 16)) || (NT == 512 && (BITS << LG) <= (8 << 15)))
+               ? 8 : 1;
 }
 
 // One (query, tile) pair: the whole of Algorithm 1 over the tile's part of
@@ -625,75 +628,96 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     // fewer than 256 dwords that is past 16 runs or more on average, and the
     // cursor finds its run by a galloping search instead of run by run.
     const bool short_runs = total_dw < 256u * s;
-    // dword offsets (in the tile) of the U pieces that start at stream
-    // position cb; the cursor only moves forward, and pieces past the end
-    // read the tile's trailing padding dwords
-    uint32_t off[U];
-    auto piece_offsets = [&](uint32_t cb) {
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                const uint32_t p0 = cb + u * 64;
-                if (p0 >= total_dw) {
-                    off[u] = sent_dw + lane;
+    // move the cursor to the run holding stream position p0 < total_dw
+    auto seek = [&](uint32_t p0) {
+        if (p0 >= c_hi) {
+            si++;
+            c_lo = c_hi;
+            c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
+            if (p0 >= c_hi) {
+                if (short_runs) {
+                    si = __builtin_amdgcn_readfirstlane(
+                        last_run_at_or_before((lds_u32 *)sp_cum, si + 1, s, p0));
+                    c_lo = __builtin_amdgcn_readfirstlane(sp_cum[si]);
+                    c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
                 } else {
-                    if (p0 >= c_hi) {   // the run holding p0
+                    while (p0 >= c_hi) {   // runs of no dwords are skipped
                         si++;
                         c_lo = c_hi;
                         c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
-                        if (p0 >= c_hi) {
-                            if (short_runs) {
-                                si = __builtin_amdgcn_readfirstlane(
-                                    last_run_at_or_before((lds_u32 *)sp_cum, si + 1, s, p0));
-                                c_lo = __builtin_amdgcn_readfirstlane(sp_cum[si]);
-                                c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
-                            } else {
-                                while (p0 >= c_hi) {   // runs of no dwords are skipped
-                                    si++;
-                                    c_lo = c_hi;
-                                    c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
-                                }
-                            }
-                        }
-                        dwb = __builtin_amdgcn_readfirstlane(sp_dw[si]);
-                    }
-                    if (p0 + 64 <= c_hi) {
-                        off[u] = (dwb + (p0 - c_lo)) + lane;   // scalar part + lane
-                    } else {   // the piece reaches into later runs or past the end
-                        const uint32_t pos = p0 + lane;
-                        if (pos < total_dw) {
-                            uint32_t li = si, l_lo = c_lo, l_hi = c_hi, l_dwb = dwb;
-                            while (pos >= l_hi) {
-                                li++;
-                                l_lo = l_hi;
-                                l_hi = sp_cum[li + 1];
-                                l_dwb = sp_dw[li];
-                            }
-                            off[u] = l_dwb + (pos - l_lo);
-                        } else {
-                            off[u] = sent_dw + lane;
-                        }
                     }
                 }
             }
+            dwb = __builtin_amdgcn_readfirstlane(sp_dw[si]);
+        }
+    };
+    // Byte offsets (from the tile's first posting) of the lane's dword in
+    // each of the U pieces of the wave's step at stream position cb; the
+    // cursor only moves forward, and pieces past the end read the tile's
+    // trailing padding dwords.  When the step's CH dwords lie inside one run
+    // (the common case with long runs) an offset is one scalar base plus the
+    // lane's fixed offset, a single vector add; otherwise each piece is
+    // placed on its own, and a piece that reaches into later runs or past
+    // the end is placed lane by lane.
+    const uint32_t lane4 = lane * 4;
+    uint32_t off4[U];
+    auto step_offsets = [&](uint32_t cb) {
+        if (cb < total_dw)
+            seek(cb);
+        if (cb + CH <= c_hi) {
+            const uint32_t sb = (dwb + (cb - c_lo)) * 4;
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                off4[u] = (sb + 256u * u) + lane4;
+            return;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t p0 = cb + u * 64;
+            uint32_t off;
+            if (p0 >= total_dw) {
+                off = sent_dw + lane;
+            } else {
+                seek(p0);
+                if (p0 + 64 <= c_hi) {
+                    off = (dwb + (p0 - c_lo)) + lane;   // scalar part + lane
+                } else {
+                    const uint32_t pos = p0 + lane;
+                    if (pos < total_dw) {
+                        uint32_t li = si, l_lo = c_lo, l_hi = c_hi, l_dwb = dwb;
+                        while (pos >= l_hi) {
+                            li++;
+                            l_lo = l_hi;
+                            l_hi = sp_cum[li + 1];
+                            l_dwb = sp_dw[li];
+                        }
+                        off = l_dwb + (pos - l_lo);
+                    } else {
+                        off = sent_dw + lane;
+                    }
+                }
+            }
+            off4[u] = off * 4;
+        }
     };
     // Software pipelining: each step issues the next step's posting loads
     // before its own counting, so the load latency (from L2, the Infinity
     // Cache or HBM) overlaps the LDS atomics; the scheduling barrier keeps
     // the compiler from sinking those loads below the atomics.
     uint32_t nv[U];
-    piece_offsets(wave * CH);
+    step_offsets(wave * CH);
 #pragma unroll
     for (int u = 0; u < U; u++)   // uniform 64-bit base + 32-bit byte offset
-        nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + (off[u] << 2));
+        nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + off4[u]);
     for (uint32_t cb = wave * CH; cb < total_dw; cb += NWAVE * CH) {
         uint32_t v[U];
 #pragma unroll
         for (int u = 0; u < U; u++)
             v[u] = nv[u];
-        piece_offsets(cb + NWAVE * CH);
+        step_offsets(cb + NWAVE * CH);
 #pragma unroll
         for (int u = 0; u < U; u++)
-            nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + (off[u] << 2));
+            nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + off4[u]);
         __builtin_amdgcn_sched_barrier(0);
         uint32_t at_reg = lds_load(&misc[M_AT]);
         const uint32_t at_m1 = at_reg - 1;   // val = f + 1 >= AT  <=>  f >= AT - 1
@@ -1021,7 +1045,8 @@ void scan_cpq_kernel(ScanParams p) {
             prepare_pair(p, smem, tables, tables + p.max_items, smem + M_SLOT);
         __syncthreads();
         for (uint32_t slot = 0;; slot ^= 1u) {
-            const uint32_t pair = smem[M_SLOT + slot * H_WORDS + H_PAIR];
+            const uint32_t pair =
+                __builtin_amdgcn_readfirstlane(smem[M_SLOT + slot * H_WORDS + H_PAIR]);
             if (pair == kNoPair)
                 break;
             scan_pair<BITS, NT, U, DUMP, LG, SPQ, true>(p, pair, bc, smem, slot);
