@@ -134,7 +134,7 @@ __device__ __attribute__((noinline)) uint32_t last_run_at_or_before(lds_u32 *sp_
 // misc words at the start of the LDS block
 enum : int {
     M_AT = 0, M_NABOVE = 1, M_OVERFLOW = 2, M_INSERTS = 3, M_SCANNED = 4, M_PASSES = 5,
-    M_PREFETCH = 6, M_WAVESUM = 8,
+    M_PREFETCH = 6, M_TAIL = 7, M_WAVESUM = 8,
     // cleared for every pair: words below M_KEEP; the persistent schedule keeps
     // its state above: two run-table slot headers and its claim cursor
     M_KEEP = 24, M_SLOT = 24, M_XCD = 30, M_SPENT = 31
@@ -704,17 +704,33 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     // before its own counting, so the load latency (from L2, the Infinity
     // Cache or HBM) overlaps the LDS atomics; the scheduling barrier keeps
     // the compiler from sinking those loads below the atomics.
+    // Chunks of CH dwords: the first ones go to the waves in turn, the last
+    // quarter (at least one per wave) is taken by the waves that get there
+    // first, one LDS claim per chunk, so the waves end together.
+    const uint32_t n_chunks = (total_dw + CH - 1) / CH;
+    const uint32_t tail = max(n_chunks / 4, (uint32_t)NWAVE);
+    const uint32_t c_static = n_chunks > tail ? n_chunks - tail : 0u;
+    auto next_chunk = [&](uint32_t c) -> uint32_t {
+        if (c + NWAVE < c_static)
+            return c + NWAVE;
+        uint32_t x = 0;
+        if (lane == 0)
+            x = lds_add(&misc[M_TAIL], 1u);
+        return c_static + __builtin_amdgcn_readfirstlane(x);
+    };
+    uint32_t cc = wave < c_static ? wave : next_chunk(c_static);
     uint32_t nv[U];
-    step_offsets(wave * CH);
+    step_offsets(cc * CH);
 #pragma unroll
     for (int u = 0; u < U; u++)   // uniform 64-bit base + 32-bit byte offset
         nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + off4[u]);
-    for (uint32_t cb = wave * CH; cb < total_dw; cb += NWAVE * CH) {
+    for (; cc < n_chunks;) {
         uint32_t v[U];
 #pragma unroll
         for (int u = 0; u < U; u++)
             v[u] = nv[u];
-        step_offsets(cb + NWAVE * CH);
+        cc = next_chunk(cc);
+        step_offsets(cc * CH);
 #pragma unroll
         for (int u = 0; u < U; u++)
             nv[u] = *reinterpret_cast<const uint32_t *>(tile_bytes + off4[u]);
