@@ -156,8 +156,9 @@ def roofs(scanned, s_total, nq, k, n_tiles, kernel_ms, peaks, traffic):
     addresses look like (about half the conflict-free rate).  When the
     algorithmic bytes arrive faster than HBM can deliver them (the layout
     moves 2 B per posting and the caches serve part of them), HBM cannot be
-    the bound in these bytes; otherwise the roof with the larger fraction
-    binds."""
+    the bound in these bytes; the HBM bytes the counters measured then stand
+    for it (when a counter summary of this kernel source is present), and
+    the roof with the larger fraction binds."""
     t = kernel_ms * 1e-3
     alg = 4 * scanned + 12 * s_total + 16 * s_total + 8 * k * nq
     layout = 2 * scanned + 12 * s_total + 8 * s_total * n_tiles + 8 * k * nq
@@ -167,10 +168,17 @@ def roofs(scanned, s_total, nq, k, n_tiles, kernel_ms, peaks, traffic):
     lds_peak = peaks["lds_atomic_conflict_free"]
     lds_frac = rate / lds_peak
     hbm_binds = hbm_frac <= 1.0 and hbm_frac >= lds_frac
+    meas_frac = traffic / t / 1e9 / HBM_PEAK_GBS if traffic else None
     out = {"kernel": "scan_cpq_kernel", "kernel_ms": round(kernel_ms, 4)}
     if hbm_binds:
         out.update(bound="hbm", achieved=round(hbm_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                   frac=round(hbm_frac, 4))
+                   frac=round(hbm_frac, 4), achieved_bytes="algorithmic")
+    elif hbm_frac > 1.0 and meas_frac is not None and meas_frac >= lds_frac:
+        out.update(bound="hbm", achieved=round(traffic / t / 1e9, 1), peak=HBM_PEAK_GBS,
+                   unit="GB/s", frac=round(meas_frac, 4),
+                   achieved_bytes="measured HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                  "calibrated): the algorithmic bytes exceed what HBM can "
+                                  "deliver, the L2 and Infinity Cache serving part of them")
     else:
         out.update(bound="lds_atomic", achieved=round(rate / 1e9, 1),
                    peak=round(lds_peak / 1e9, 1), unit="G atomic adds/s",
@@ -449,6 +457,8 @@ class SearchBench:
         if self.plain_shape:
             g.genie_index_set_scan_shape(self.ix, *self.plain_shape[:2])
             g.genie_index_set_scan_schedule(self.ix, self.plain_shape[2])
+        plain_shape = "%dx%d" % tuple(self.ix.info.scan_shape)
+        plain_sched = schedule_name(self.ix, self.nq)
         g.genie_kernel_timing_enable(True)
         g.genie_kernel_timing_read(reset=True)
         el_plain = eager_plain = self.timed(self.plain_step, steps, warmup)
@@ -555,8 +565,7 @@ class SearchBench:
                  "ht_inserts_per_step": stats["ht_inserts"],
                  "ht_overflow_tiles": stats["ht_overflow_tiles"],
                  "tile_objects": self.ix.info.tile_objects,
-                 "scan_shape": "%dx%d" % tuple(self.ix.info.scan_shape),
-                 "schedule": schedule_name(self.ix, self.nq)}
+                 "scan_shape": plain_shape, "schedule": plain_sched}
         learned = None
         if el_gate is not None:
             gms = gkt["scan_ms"] / max(1, gkt["scan_launches"])

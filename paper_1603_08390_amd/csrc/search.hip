@@ -804,10 +804,15 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                     const uint64_t m = __ballot(pass);
                     if (m) {
                         passes += (uint32_t)__popcll(m);
+                        // the ZA add and the AT read go out together (one
+                        // LDS round trip); AT is read again only after an
+                        // advance of this wave's own
                         const uint32_t zc = pass ? lds_add(&za[val], 1u) + 1 : 0u;
-                        if (__ballot(zc >= k))
-                            advance_at(za, misc, k, s);
                         at_reg = lds_load(&misc[M_AT]);
+                        if (__ballot(zc >= k)) {
+                            advance_at(za, misc, k, s);
+                            at_reg = lds_load(&misc[M_AT]);
+                        }
                         const bool keep = pass && val >= at_reg;
                         const uint64_t mk = __ballot(keep);
                         if (mk) {
