@@ -610,7 +610,10 @@ def line(args, workload, res, config, dtype="u32"):
            "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic",
            "config": dict(config, path=res["path"], launch=res["launch"],
-                          parallelism="single GPU")}
+                          parallelism="single GPU",
+                          step="the index, the queries, the answers and the workspace are "
+                               "resident in HBM; host-device copies are outside the timed "
+                               "step (the serving line's latencies include them)")}
     for key in ("roofline", "atomic_roof", "plain_cpq", "learned_gate", "gen_spq"):
         out[key] = res[key]
     out["peaks"] = args.peaks
