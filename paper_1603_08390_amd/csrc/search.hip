@@ -798,6 +798,9 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
             for (int u = 0; u < U; u++)
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
+                    // a slot none of whose lanes reach AT costs one compare
+                    if (!__ballot(f[2 * u + h] + 1 >= at_reg))
+                        continue;
                     const uint32_t lid = h ? (v[u] >> 16) : (v[u] & 0xFFFFu);
                     const uint32_t val = f[2 * u + h] + 1;
                     const bool pass = val >= at_reg && lid != SENT;
