@@ -104,31 +104,27 @@ __device__ __forceinline__ bool lds_cas(uint32_t *p, uint32_t expect, uint32_t d
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// The last run starting at or before p0, given lo with sp_cum[lo] <= p0 and
-// p0 < sp_cum[s] (the run starts ascend): a galloping search from lo, then
-// bisection.  The run found is never empty, since the run after it starts
-// past p0.  Kept out of line: it serves the long jumps of the run cursor
-// over short runs.
+// The run holding stream position p0, for a cursor at run `si` that ends at
+// or before p0 (p0 < sp_cum[s]): the ends of the next 64 runs, one per lane
+// (lane 0 reads the cursor's own end); the first end past p0 closes the run
+// holding p0.  Returns that run and its bounds {run, start, end}.  Kept out
+// of line: it serves the long jumps of the run cursor over short runs.
+// Wave-uniform call with every lane active.
 typedef __attribute__((address_space(3))) const uint32_t lds_u32;   // an LDS word
-__device__ __attribute__((noinline)) uint32_t last_run_at_or_before(lds_u32 *sp_cum, uint32_t lo,
-                                                                    uint32_t s, uint32_t p0) {
-    uint32_t hi = s, step = 1;   // sp_cum[lo] <= p0 < sp_cum[hi]
-    while (lo + step < s) {
-        if (sp_cum[lo + step] > p0) {
-            hi = lo + step;
-            break;
+__device__ __attribute__((noinline)) uint3 run_holding(lds_u32 *sp_cum, uint32_t si, uint32_t s,
+                                                       uint32_t p0) {
+    const uint32_t lane = threadIdx.x & 63;
+    for (;;) {
+        const uint32_t idx = si + 1 + lane;
+        const uint32_t w = idx <= s ? sp_cum[idx] : 0xFFFFFFFFu;
+        const uint64_t m = __ballot(w > p0);
+        if (m) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(m);   // >= 1
+            return make_uint3(si + j, __builtin_amdgcn_readlane(w, j - 1),
+                              __builtin_amdgcn_readlane(w, j));
         }
-        lo += step;
-        step <<= 1;
+        si += 63;   // run si + 63 ends at or before p0
     }
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (sp_cum[mid] <= p0)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
 }
 
 // misc words at the start of the LDS block
@@ -636,10 +632,10 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
             c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
             if (p0 >= c_hi) {
                 if (short_runs) {
-                    si = __builtin_amdgcn_readfirstlane(
-                        last_run_at_or_before((lds_u32 *)sp_cum, si + 1, s, p0));
-                    c_lo = __builtin_amdgcn_readfirstlane(sp_cum[si]);
-                    c_hi = __builtin_amdgcn_readfirstlane(sp_cum[si + 1]);
+                    const uint3 r = run_holding((lds_u32 *)sp_cum, si, s, p0);
+                    si = __builtin_amdgcn_readfirstlane(r.x);
+                    c_lo = __builtin_amdgcn_readfirstlane(r.y);
+                    c_hi = __builtin_amdgcn_readfirstlane(r.z);
                 } else {
                     while (p0 >= c_hi) {   // runs of no dwords are skipped
                         si++;
