@@ -156,9 +156,12 @@ def roofs(scanned, s_total, nq, k, n_tiles, kernel_ms, peaks, traffic):
     addresses look like (about half the conflict-free rate).  When the
     algorithmic bytes arrive faster than HBM can deliver them (the layout
     moves 2 B per posting and the caches serve part of them), HBM cannot be
-    the bound in these bytes; the HBM bytes the counters measured then stand
-    for it (when a counter summary of this kernel source is present), and
-    the roof with the larger fraction binds."""
+    the bound in these bytes.  With a counter summary of this kernel
+    source present, the roof with the larger fraction of the two measured
+    rates binds -- the HBM bytes the counters saw, and the atomics -- and
+    an HBM roof whose algorithmic bytes exceed HBM's rate reports the
+    measured bytes as achieved; without one, HBM binds only when the
+    algorithmic bytes fit under its peak and their fraction is the larger."""
     t = kernel_ms * 1e-3
     alg = 4 * scanned + 12 * s_total + 16 * s_total + 8 * k * nq
     layout = 2 * scanned + 12 * s_total + 8 * s_total * n_tiles + 8 * k * nq
@@ -167,13 +170,16 @@ def roofs(scanned, s_total, nq, k, n_tiles, kernel_ms, peaks, traffic):
     rate = scanned / t
     lds_peak = peaks["lds_atomic_conflict_free"]
     lds_frac = rate / lds_peak
-    hbm_binds = hbm_frac <= 1.0 and hbm_frac >= lds_frac
     meas_frac = traffic / t / 1e9 / HBM_PEAK_GBS if traffic else None
+    if meas_frac is not None:   # the counters say how much HBM actually moved
+        hbm_binds = meas_frac >= lds_frac
+    else:
+        hbm_binds = hbm_frac <= 1.0 and hbm_frac >= lds_frac
     out = {"kernel": "scan_cpq_kernel", "kernel_ms": round(kernel_ms, 4)}
-    if hbm_binds:
+    if hbm_binds and hbm_frac <= 1.0:
         out.update(bound="hbm", achieved=round(hbm_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                    frac=round(hbm_frac, 4), achieved_bytes="algorithmic")
-    elif hbm_frac > 1.0 and meas_frac is not None and meas_frac >= lds_frac:
+    elif hbm_binds:
         out.update(bound="hbm", achieved=round(traffic / t / 1e9, 1), peak=HBM_PEAK_GBS,
                    unit="GB/s", frac=round(meas_frac, 4),
                    achieved_bytes="measured HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
