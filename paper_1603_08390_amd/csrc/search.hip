@@ -599,11 +599,12 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     }
 
     // ---- scan: every posting of every run adds one to its object's count.
-    // The runs' dwords form one stream cut into 64-dword pieces; lane l of a
-    // wave takes dword l of a piece (two postings), so the ids that
-    // neighbouring lanes touch ascend together and spread over neighbouring
-    // LDS banks.  The run cursor is the same in every lane: a piece inside
-    // one run is addressed as cursor + lane.  Runs are padded with the
+    // The runs' dwords form one stream cut into 64-dword pieces; a wave's
+    // step takes U consecutive pieces (a chunk of CH dwords), and lane l
+    // takes dword l of each piece (two postings); the build orders each run
+    // so that the ids the lanes of one step touch sit in different LDS
+    // banks.  The run cursor is the same in every lane: a piece inside one
+    // run is addressed as cursor + lane.  Runs are padded with the
     // reserved padding id 2^LG - 1, whose counter is a dummy (the top field of the
     // last word, where carries fall off), so every element is counted
     // without a bounds test; lanes past the end read the tile's trailing
@@ -620,9 +621,11 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
     uint32_t si = 0, c_lo = 0;
     uint32_t c_hi = s ? __builtin_amdgcn_readfirstlane(sp_cum[1]) : 0u;
     uint32_t dwb = s ? __builtin_amdgcn_readfirstlane(sp_dw[0]) : 0u;
-    // A wave's next piece lies NWAVE pieces ahead; when the runs average
-    // fewer than 256 dwords that is past 16 runs or more on average, and the
-    // cursor finds its run by a galloping search instead of run by run.
+    // A wave's next chunk lies NWAVE chunks ahead (or further, for a chunk
+    // claimed at the tail); when the runs average fewer than 256 dwords that
+    // is past 16 runs or more on average, and the cursor finds its run from
+    // the ends of the next 64 runs at once (run_holding) instead of run by
+    // run.
     const bool short_runs = total_dw < 256u * s;
     // move the cursor to the run holding stream position p0 < total_dw
     auto seek = [&](uint32_t p0) {
