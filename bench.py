@@ -662,6 +662,7 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
                           tune["plain"]["persistent"])
     if not args.no_gate:
         tq = train_queries(np.random.default_rng(workloads.BASE_SEED + 100 + workloads.CONFIG_IDS[name]))
+        n_train = tq.n_queries
         toff, titems = genie.queries_to_device(tq.q_offsets, tq.items)
         sb.model = train_gate(genie, torch, ix, [(toff, titems, tq.max_items(), k)],
                               args.gate_epochs, args)
@@ -686,7 +687,7 @@ def bench_item_queries(args, torch, genie, workloads, name, inst, train_queries,
         # per path, per tiling (tile_log2), per scan shape
         out["autotune_ms"] = {path: t["ms"] for path, t in tune.items()}
     if out["learned_gate"]:
-        out["learned_gate"].update(train_queries=args.gate_train_queries,
+        out["learned_gate"].update(train_queries=n_train,
                                    epochs=args.gate_epochs)
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline and args.cpu_budget > 0:
@@ -726,7 +727,8 @@ def bench_uneven(args, torch, genie, workloads):
     inst = workloads.uneven()
     return bench_item_queries(
         args, torch, genie, workloads, "uneven", inst,
-        lambda rng: workloads.queries_uneven(rng, inst.values, inst.V, args.gate_train_queries),
+        lambda rng: workloads.queries_uneven(rng, inst.values, inst.V,
+                                             args.gate_train_queries_uneven),
         "uneven: 10,000,000 objects x 64 dims, per-dim Zipf(1.1) over 1,024 buckets; 16,384 "
         "queries of U{4..512} range items in one launch; k=100", tune_sample=1024, chunk=1)
 
@@ -1324,6 +1326,8 @@ def main():
                     help="time HIP graph replays of the step (auto: on); kernel durations "
                          "always come from an eager pass of the same steps")
     ap.add_argument("--gate-train-queries", type=int, default=4096)
+    ap.add_argument("--gate-train-queries-uneven", type=int, default=16384,
+                    help="queries the gate is trained on for the uneven workload")
     ap.add_argument("--gate-epochs", type=int, default=30)
     ap.add_argument("--fixed", default=None, metavar="L,T,U,P",
                     help="item workloads: tiles of 2^L-1 objects, T threads x U dwords, "

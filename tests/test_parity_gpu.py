@@ -90,6 +90,46 @@ def test_relational_several_tiles_ragged(k, schedule):
     ix.free()
 
 
+@pytest.mark.parametrize("schedule", [1, 0])
+def test_short_runs_cursor_jumps_past_many_runs(schedule):
+    """Streams with short runs on average: the run cursor finds its run from
+    the ends of the next 64 runs at once, and moves on by 63 runs when none
+    of them holds the position.  Most of the 500 items of a query name values
+    no object holds (empty runs); about one in 70 names some of the 8 values
+    every object holds, so consecutive non-empty runs lie more than 64 runs
+    apart.  Two tiles, the second ragged; plain and gated (the gate set too
+    high, so the exact fallback answers every query) searches."""
+    rng = np.random.default_rng(20261203)
+    n, d, V, nq, s, k = 70_000, 4, 512, 40, 500, 50
+    values = rng.integers(0, 8, size=(n, d), dtype=np.uint32)
+    items = np.zeros((nq * s, 3), np.uint32)
+    for q in range(nq):
+        for i in range(s):
+            row = items[q * s + i]
+            row[0] = i % d
+            if (i + q) % 70 == 0:
+                row[1] = rng.integers(0, 8)
+                row[2] = row[1] + rng.integers(0, 3)
+            else:
+                row[1] = row[2] = rng.integers(100, 500)
+    queries = workloads.Queries(np.arange(0, nq * s + 1, s, dtype=np.uint64), items)
+    print("short runs, cursor jumps; schedule", schedule, flush=True)
+    ix = genie.Index(values, V)
+    genie.genie_index_set_scan_schedule(ix, schedule)
+    _check(values, V, queries, k, ix=ix)
+    oidx = oracle.build_csr(values, V)
+    o_ids, o_cts, _, _ = oracle.search_idx(oidx, queries, k)
+    off, d_items = genie.queries_to_device(queries.q_offsets, queries.items)
+    high = torch.full((nq,), 1e9, dtype=torch.float32, device="cuda")
+    g_ids, g_cts, ws = genie.genie_search_gated_async(ix, off, d_items, k, s, high, 0.0)
+    torch.cuda.synchronize()
+    st = genie.workspace_stats(ws)
+    assert st["status"] == 0 and st["fallback_queries"] == nq, st
+    assert np.array_equal(genie.as_uint32(g_ids), o_ids)
+    assert np.array_equal(genie.as_uint32(g_cts), o_cts)
+    ix.free()
+
+
 def test_uneven_items_scaled():
     inst = workloads.uneven(n=140_000, d=16, V=64, nq=40, smin=1, smax=200)
     print("uneven scaled", inst.n, inst.queries.max_items(), flush=True)
