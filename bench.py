@@ -88,9 +88,6 @@ METRICS = {
                 "and certificate included; learned-gate vs plain c-PQ",
 }
 HBM_PEAK_GBS = 8000.0
-# Conflict-free LDS atomic add (with return), lane-consecutive addresses,
-# measured on MI355X: 8.34e12/s over the chip (13.6 per CU per 2.4 GHz clock).
-LDS_ATOMIC_PEAK = 8.34e12
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1603_08390_amd", "csrc", "search.hip")
 
 
