@@ -285,14 +285,15 @@ __device__ void ht_put(uint32_t *ht, uint32_t lg, uint32_t *misc, uint32_t lid, 
     }
 }
 
-// Number of the BITS-bit fields of `word` equal to v among those whose ids
-// (first, first + 1, ...) are below n.  Exact zero-field test: in x = word
-// xor (v in every field), a field is non-zero iff its high bit is set or its
-// low bits are; adding the low-bits mask to the low bits sets the high bit
-// exactly when they are non-zero (no carry leaves a field).
+// The BITS-bit fields of `word` equal to v among those whose ids (first,
+// first + 1, ...) are below n, as the high bit of each such field.  Exact
+// zero-field test: in x = word xor (v in every field), a field is non-zero
+// iff its high bit is set or its low bits are; adding the low-bits mask to
+// the low bits sets the high bit exactly when they are non-zero (no carry
+// leaves a field).
 template <int BITS>
-__device__ __forceinline__ uint32_t fields_equal(uint32_t word, uint32_t v, uint32_t n,
-                                                 uint32_t first) {
+__device__ __forceinline__ uint32_t fields_equal_mask(uint32_t word, uint32_t v, uint32_t n,
+                                                      uint32_t first) {
     constexpr uint32_t CPW = 32 / BITS;
     constexpr uint32_t ONES = BITS == 4 ? 0x11111111u : (BITS == 8 ? 0x01010101u : 0x00010001u);
     constexpr uint32_t HI = ONES << (BITS - 1);
@@ -301,7 +302,14 @@ __device__ __forceinline__ uint32_t fields_equal(uint32_t word, uint32_t v, uint
     uint32_t zero = ~nonzero & HI;
     if (first + CPW > n)   // fields at or past n are not objects of the tile
         zero &= n > first ? HI >> ((CPW - (n - first)) * BITS) : 0u;
-    return __popc(zero);
+    return zero;
+}
+
+// Number of those fields.
+template <int BITS>
+__device__ __forceinline__ uint32_t fields_equal(uint32_t word, uint32_t v, uint32_t n,
+                                                 uint32_t first) {
+    return __popc(fields_equal_mask<BITS>(word, v, n, first));
 }
 
 constexpr uint32_t ilog2(uint32_t x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
@@ -1000,16 +1008,16 @@ __device__ __forceinline__ void scan_pair(const ScanParams &p, uint64_t pair, ui
                 for (uint32_t u = 0; u < B; u++)
                     wd[u] = bc[w0 + u];
 #pragma unroll
-                for (uint32_t u = 0; u < B; u++)
-#pragma unroll
-                    for (uint32_t f = 0; f < CPW; f++) {
-                        const uint32_t lid = (w0 + u) * CPW + f;
-                        if (lid < tile_n && ((wd[u] >> (f * BITS)) & MASK) == thr) {
-                            if (r < need)
-                                out[n_above + r] = make_key(thr, (uint32_t)(gid0 + lid));
-                            r++;
-                        }
+                for (uint32_t u = 0; u < B; u++) {
+                    // the word's tied fields in id order, one bit each
+                    uint32_t z = fields_equal_mask<BITS>(wd[u], thr, tile_n, (w0 + u) * CPW);
+                    while (z != 0 && r < need) {
+                        const uint32_t f = (uint32_t)__builtin_ctz(z) >> LBITS;
+                        z &= z - 1;
+                        out[n_above + r] = make_key(thr, (uint32_t)(gid0 + (w0 + u) * CPW + f));
+                        r++;
                     }
+                }
             }
         }
     }
